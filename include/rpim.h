@@ -1,0 +1,169 @@
+/*
+ * rpim.h -- C ABI of the MI355X RPIM global-stiffness assembly library.
+ *
+ * The library assembles the global stiffness matrix K of 3D linear elasticity
+ * with the radial point interpolation method, point by point over background
+ * Gauss points (GeoMFree3D, Sec. 2, stage 1), and enforces displacement
+ * boundary conditions by the penalty method (Sec. 2, stage 2).  The paper
+ * prints no formulas; the method is Liu's polynomial-augmented RPIM cited in
+ * Sec. 1, written out here:
+ *
+ *   for each Gauss point g at x_g with weight w_g (Gauss weight * |J|) in cell c:
+ *     S_g  = { i : |x_i - x_g|^2 <= d_s^2 }, sorted by node id          (support)
+ *     G_g  = [[R, P], [P^T, 0]],  R_ab = (|x_a - x_b|^2 + (alpha_c d_c)^2)^q,
+ *            P_a = [1, x_a - x_g]                                       (moment matrix)
+ *     G_g gamma_k = d/dx_k [R(x); 1, x - x_g] at x_g,  dphi_a/dx_k = gamma_k[a]
+ *     k^g_ab = w_g E_c [lam phi_a phi_b^T + mu phi_b phi_a^T + mu (phi_a . phi_b) I3]
+ *            (= B_a^T D B_b for isotropic D; lam, mu for E = 1 and the given nu)
+ *   K = sum_g scatter(k^g) into a CSR matrix over dof = 3*node + component.
+ *
+ * Conventions shared by every call
+ *   - Pointers are DEVICE pointers unless marked [host].  All arrays are
+ *     C-contiguous.  The caller owns every buffer it passes; the library never
+ *     frees them.  A plan owns the device memory it allocates itself.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   - Errors in arguments are returned synchronously.  Errors found on the
+ *     device (a support with fewer than 5 nodes, a singular moment matrix, a
+ *     power too close to a rounding boundary to round correctly) are recorded
+ *     in the plan with the smallest failing Gauss-point id and reported by
+ *     rpim_get_status(); K values of failing points are then undefined.
+ *   - Every output is a deterministic function of the inputs: no floating
+ *     point atomics, every K entry is summed over contributing Gauss points in
+ *     ascending Gauss-point id.  On the FP64 path the result is bitwise equal
+ *     to a serial evaluation in the same operation order (correctly rounded
+ *     power, IEEE division, explicit fma, no other contraction).
+ */
+#ifndef RPIM_H
+#define RPIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPIM_OK = 0,
+  RPIM_E_ARG = -1,      /* invalid argument                                     */
+  RPIM_E_NOMEM = -2,    /* device allocation failed                             */
+  RPIM_E_HIP = -3,      /* HIP runtime error                                    */
+  RPIM_E_SUPPORT = -4,  /* a Gauss point has fewer than 5 support nodes         */
+  RPIM_E_SINGULAR = -5, /* |u_kk| <= N * eps * max|G| during the LU             */
+  RPIM_E_RANGE = -6,    /* a size exceeds a documented limit                    */
+  RPIM_E_POW = -7,      /* a power could not be rounded correctly (never seen)  */
+  RPIM_E_STATE = -8     /* call order violated (e.g. backward before assemble)  */
+} rpim_status;
+
+typedef enum {
+  RPIM_FP64 = 0,  /* K is double[nnz]; everything FP64                         */
+  RPIM_MIXED = 1  /* K is float[nnz]: FP64 moment matrix + LU, FP32 B^T D B,
+                     FP32 Kahan-compensated accumulation                       */
+} rpim_precision;
+
+/* One model, or a block-diagonal batch of independent models.
+ * Node, Gauss-point and cell ids are global over the batch; model m owns
+ * nodes [node_off[m], node_off[m+1]) and Gauss points [gp_off[m], gp_off[m+1]),
+ * and its Gauss points search only its own nodes. */
+typedef struct {
+  int32_t n_models;             /* >= 1                                              */
+  const int64_t* node_off;      /* [host] n_models + 1 prefix offsets (node_off[0] = 0) */
+  const int64_t* gp_off;        /* [host] n_models + 1                                */
+  int64_t n_cells;              /* number of cells (length of cell_E)                 */
+  const double* support_radius; /* [host] d_s per model, > 0                          */
+  const double* node_xyz;       /* [N][3] build-time node coordinates                 */
+  const double* gp_xyz;         /* [G][3] Gauss-point coordinates                     */
+  const double* gp_wdet;        /* [G] Gauss weight * |J| (> 0)                       */
+  const int32_t* gp_cell;       /* [G] cell id of each Gauss point, in [0, n_cells)   */
+  double alpha_c, d_c, q;       /* MQ basis (r^2 + (alpha_c d_c)^2)^q; all > 0        */
+} rpim_problem;
+
+typedef struct rpim_plan rpim_plan; /* opaque; owns device memory for supports etc. */
+
+/* Sizes of a built plan (filled by rpim_plan_info). */
+typedef struct {
+  int64_t n_nodes, n_gp, n_cells, n_models;
+  int64_t sum_n;       /* total support entries sum_g |S_g|                       */
+  int64_t nnz;         /* scalar nonzeros of K (9 x node-block nonzeros)          */
+  int64_t n_blocks;    /* node-block nonzeros                                     */
+  int32_t min_n, max_n;/* support sizes                                           */
+  int64_t lu_doubles;  /* doubles needed to keep LU factors (keep_factors = 1)    */
+  int32_t n_buckets;   /* support-size buckets used by the solver kernels         */
+} rpim_info;
+
+/* Create a plan: validates the problem and copies the Gauss-point arrays to
+ * plan-owned device memory (so the caller may free theirs).  No kernels run.
+ * Returns RPIM_E_ARG for NULL pointers, non-positive sizes or parameters, or
+ * offsets that are not non-decreasing and consistent. */
+rpim_status rpim_plan_create(const rpim_problem* problem, rpim_plan** plan);
+
+/* Support search and sparsity pattern (one-time per geometry; synchronous).
+ *   S_g = { i in model(g) : s_ig <= fl(d_s * d_s) },
+ *   s_ig = fma(dz, dz, fma(dy, dy, dx * dx)), d = x_i - x_g per component,
+ *   sorted by node id; the node-block pattern is the union of S_g x S_g over g
+ *   (symmetric, diagonal included), expanded to scalar CSR with columns sorted.
+ * The first call builds the plan's supports and pattern and writes *nnz.
+ * When row_ptr and col_idx are non-NULL they are filled:
+ *   row_ptr int64[3N + 1], col_idx int32[nnz] (device).
+ * Typical use: call once with NULLs to learn nnz, allocate, call again.
+ * RPIM_E_SUPPORT if some |S_g| < 5 (rpim_get_status gives the first such g);
+ * RPIM_E_RANGE if a support exceeds 256 nodes, a node lies in more than 8192
+ * supports, or the node ids in a node's neighbourhood span more than 2^18. */
+rpim_status rpim_build_pattern(rpim_plan* plan, int64_t* row_ptr, int32_t* col_idx, int64_t* nnz,
+                               void* stream);
+
+/* Stage 1, forward (asynchronous).  node_xyz [N][3] may differ from the
+ * build-time coordinates: supports and pattern stay frozen.  cell_E [n_cells],
+ * 0 < nu < 0.5 (nu > -1 accepted).  K_vals: double[nnz] (RPIM_FP64) or
+ * float[nnz] (RPIM_MIXED), fully overwritten.  keep_factors = 1 keeps the LU
+ * factors, pivots and solutions of every Gauss point in plan memory for
+ * rpim_assemble_backward (rpim_info.lu_doubles doubles). */
+rpim_status rpim_assemble(rpim_plan* plan, const double* node_xyz, const double* cell_E, double nu,
+                          int precision, int keep_factors, void* K_vals, void* stream);
+
+/* Adjoint of rpim_assemble (asynchronous).  dK_vals double[nnz] = dL/dK on the
+ * pattern (any values, not necessarily symmetric).  Writes dE_cell [n_cells] =
+ * dL/dE_c and dX_node [N][3] = dL/dx_i, with Gauss points, weights and supports
+ * held fixed.  Reuses the LU factors kept by the last rpim_assemble call with
+ * keep_factors = 1 (RPIM_E_STATE otherwise); node_xyz, cell_E and nu must be
+ * the ones that call used. */
+rpim_status rpim_assemble_backward(rpim_plan* plan, const double* node_xyz, const double* cell_E,
+                                   double nu, const double* dK_vals, double* dE_cell, double* dX_node,
+                                   void* stream);
+
+/* Stage 2: penalty boundary conditions (GeoMFree3D Sec. 2; one GPU thread per
+ * fixed dof).  alpha = factor * max_i K_ii over all n_dof diagonals (before the
+ * update); K_dd += alpha and, if rhs != NULL, rhs_d += alpha * u_bar_d
+ * (u_bar may be NULL = zero).  fixed_dof int32[n_fixed] must be strictly
+ * ascending and in [0, n_dof) (checked, RPIM_E_ARG; the check synchronises).
+ * K_vals is double or float per `precision`; for float, K_dd += (float)alpha.
+ * If alpha_out != NULL the value of alpha is written there (host). */
+rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals,
+                                  int precision, int64_t n_dof, const int32_t* fixed_dof,
+                                  const double* u_bar, int64_t n_fixed, double factor, double* rhs,
+                                  double* alpha_out, void* stream);
+
+/* Synchronise `stream` and report device-side errors of the plan's last calls:
+ * the most severe status and the smallest failing Gauss-point id (-1 if none).
+ * Clears the record. */
+rpim_status rpim_get_status(rpim_plan* plan, void* stream, int64_t* first_bad_gp);
+
+rpim_status rpim_plan_info(const rpim_plan* plan, rpim_info* info);
+
+/* Copies of plan state for inspection and tests (device outputs, async):
+ * supports gp_ptr int64[G+1], gp_nbr int32[sum_n]; shape-function gradients
+ * of the last assembly dphi double[sum_n][3]. */
+rpim_status rpim_get_support(const rpim_plan* plan, int64_t* gp_ptr, int32_t* gp_nbr, void* stream);
+rpim_status rpim_get_dphi(const rpim_plan* plan, double* dphi, void* stream);
+
+/* Correctly rounded x^q for n device doubles x > 0 (the kernel the assembly
+ * uses for the radial basis), for tests of the rounding contract. */
+rpim_status rpim_pow_cr(const double* x, double q, double* y, int64_t n, void* stream);
+
+void rpim_plan_destroy(rpim_plan* plan);
+const char* rpim_status_string(rpim_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPIM_H */

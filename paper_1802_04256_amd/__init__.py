@@ -1,0 +1,291 @@
+"""MI355X RPIM global-stiffness assembly: Python binding of librpim.so.
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every numerical step runs in the library's HIP kernels.
+Importing works without a GPU, but any call needs the built library and a
+GPU; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "assemble", "apply_penalty_bc", "pow_cr", "RpimError", "library_path", "FP64", "MIXED"]
+
+FP64, MIXED = 0, 1
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "librpim.so")
+
+_STATUS = {0: "RPIM_OK", -1: "RPIM_E_ARG", -2: "RPIM_E_NOMEM", -3: "RPIM_E_HIP", -4: "RPIM_E_SUPPORT",
+           -5: "RPIM_E_SINGULAR", -6: "RPIM_E_RANGE", -7: "RPIM_E_POW", -8: "RPIM_E_STATE"}
+
+
+class RpimError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        self.name = _STATUS.get(code, str(code))
+        super().__init__(f"{what}: {self.name}{(' ' + detail) if detail else ''}")
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n_models", C.c_int32), ("node_off", C.POINTER(C.c_int64)), ("gp_off", C.POINTER(C.c_int64)),
+                ("n_cells", C.c_int64), ("support_radius", C.POINTER(C.c_double)), ("node_xyz", C.c_void_p),
+                ("gp_xyz", C.c_void_p), ("gp_wdet", C.c_void_p), ("gp_cell", C.c_void_p),
+                ("alpha_c", C.c_double), ("d_c", C.c_double), ("q", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_gp", C.c_int64), ("n_cells", C.c_int64), ("n_models", C.c_int64),
+                ("sum_n", C.c_int64), ("nnz", C.c_int64), ("n_blocks", C.c_int64), ("min_n", C.c_int32),
+                ("max_n", C.c_int32), ("lu_doubles", C.c_int64), ("n_buckets", C.c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load librpim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RpimError(-3, "load", f"{_LIB_PATH} is missing; build it with __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int, C.c_double
+        L.rpim_plan_create.argtypes = [C.POINTER(_Problem), C.POINTER(vp)]
+        L.rpim_build_pattern.argtypes = [vp, vp, vp, C.POINTER(i64), vp]
+        L.rpim_assemble.argtypes = [vp, vp, vp, d, i32, i32, vp, vp]
+        L.rpim_assemble_backward.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
+        L.rpim_apply_penalty_bc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, C.POINTER(d), vp]
+        L.rpim_get_status.argtypes = [vp, vp, C.POINTER(i64)]
+        L.rpim_plan_info.argtypes = [vp, C.POINTER(_Info)]
+        L.rpim_get_support.argtypes = [vp, vp, vp, vp]
+        L.rpim_get_dphi.argtypes = [vp, vp, vp]
+        L.rpim_pow_cr.argtypes = [vp, d, vp, i64, vp]
+        L.rpim_plan_destroy.argtypes = [vp]
+        L.rpim_plan_destroy.restype = None
+        L.rpim_status_string.restype = C.c_char_p
+        for f in ("rpim_plan_create", "rpim_build_pattern", "rpim_assemble", "rpim_assemble_backward",
+                  "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
+                  "rpim_get_dphi", "rpim_pow_cr"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(code, what):
+    if code != 0:
+        raise RpimError(code, what)
+
+
+def _dev(t, dtype, device):
+    torch = _torch()
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class Plan:
+    """Supports, pattern and workspaces of one model or a block-diagonal batch."""
+
+    def __init__(self, node_xyz, gp_xyz, gp_wdet, gp_cell, n_cells, support_radius, alpha_c=4.0, d_c=1.0,
+                 q=1.03, node_off=None, gp_off=None, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.node_xyz = _dev(node_xyz, torch.float64, self.device)
+        self.gp_xyz = _dev(gp_xyz, torch.float64, self.device)
+        self.gp_wdet = _dev(gp_wdet, torch.float64, self.device)
+        self.gp_cell = _dev(gp_cell, torch.int32, self.device)
+        self.n_nodes = int(self.node_xyz.shape[0])
+        self.n_gp = int(self.gp_xyz.shape[0])
+        self.n_cells = int(n_cells)
+        node_off = np.array([0, self.n_nodes] if node_off is None else node_off, np.int64)
+        gp_off = np.array([0, self.n_gp] if gp_off is None else gp_off, np.int64)
+        radius = np.atleast_1d(np.asarray(support_radius, np.float64))
+        if radius.size == 1 and len(node_off) > 2:
+            radius = np.full(len(node_off) - 1, float(radius[0]))
+        self._node_off, self._gp_off, self._radius = node_off, gp_off, radius
+        pb = _Problem()
+        pb.n_models = len(node_off) - 1
+        pb.node_off = node_off.ctypes.data_as(C.POINTER(C.c_int64))
+        pb.gp_off = gp_off.ctypes.data_as(C.POINTER(C.c_int64))
+        pb.n_cells = self.n_cells
+        pb.support_radius = radius.ctypes.data_as(C.POINTER(C.c_double))
+        pb.node_xyz = self.node_xyz.data_ptr()
+        pb.gp_xyz = self.gp_xyz.data_ptr()
+        pb.gp_wdet = self.gp_wdet.data_ptr()
+        pb.gp_cell = self.gp_cell.data_ptr()
+        pb.alpha_c, pb.d_c, pb.q = float(alpha_c), float(d_c), float(q)
+        h = C.c_void_p()
+        _check(lib().rpim_plan_create(C.byref(pb), C.byref(h)), "rpim_plan_create")
+        self._h = h
+        self.nnz = None
+        self.row_ptr = None
+        self.col_idx = None
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda"):
+        radius = prob.meta.get("support_radius", prob.support_radius) if prob.n_models > 1 else prob.support_radius
+        return cls(prob.node_xyz, prob.gp_xyz, prob.gp_wdet, prob.gp_cell, prob.n_cells, radius,
+                   prob.alpha_c, prob.d_c, prob.q, prob.node_off, prob.gp_off, device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rpim_plan_destroy(h)
+            self._h = None
+
+    # -- pattern ------------------------------------------------------------
+    def build_pattern(self):
+        """Supports and CSR pattern (synchronous); returns (row_ptr int64, col_idx int32)."""
+        torch = _torch()
+        nnz = C.c_int64()
+        st = lib().rpim_build_pattern(self._h, None, None, C.byref(nnz), _stream())
+        if st != 0:
+            bad = C.c_int64()
+            lib().rpim_get_status(self._h, _stream(), C.byref(bad))
+            raise RpimError(st, "rpim_build_pattern", f"(first bad gauss point {bad.value})")
+        self.nnz = nnz.value
+        self.row_ptr = torch.empty(3 * self.n_nodes + 1, dtype=torch.int64, device=self.device)
+        self.col_idx = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        _check(lib().rpim_build_pattern(self._h, _ptr(self.row_ptr), _ptr(self.col_idx), C.byref(nnz), _stream()),
+               "rpim_build_pattern")
+        return self.row_ptr, self.col_idx
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().rpim_plan_info(self._h, C.byref(inf)), "rpim_plan_info")
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    # -- forward / backward ----------------------------------------------------
+    def assemble(self, node_xyz=None, cell_E=None, nu=0.3, precision=FP64, keep_factors=False, out=None):
+        torch = _torch()
+        if self.nnz is None:
+            self.build_pattern()
+        X = self.node_xyz if node_xyz is None else _dev(node_xyz, torch.float64, self.device)
+        E = _dev(cell_E, torch.float64, self.device)
+        prec = _precision(precision)
+        dt = torch.float64 if prec == FP64 else torch.float32
+        K = out if out is not None else torch.empty(self.nnz, dtype=dt, device=self.device)
+        if K.dtype != dt or K.numel() != self.nnz or not K.is_contiguous():
+            raise RpimError(-1, "rpim_assemble", "output has wrong dtype/size")
+        _check(lib().rpim_assemble(self._h, _ptr(X), _ptr(E), float(nu), prec, int(bool(keep_factors)), _ptr(K),
+                                   _stream()), "rpim_assemble")
+        return K
+
+    def assemble_backward(self, node_xyz, cell_E, nu, dK):
+        torch = _torch()
+        X = _dev(node_xyz, torch.float64, self.device)
+        E = _dev(cell_E, torch.float64, self.device)
+        dK = _dev(dK, torch.float64, self.device)
+        dE = torch.empty(self.n_cells, dtype=torch.float64, device=self.device)
+        dX = torch.empty(self.n_nodes, 3, dtype=torch.float64, device=self.device)
+        _check(lib().rpim_assemble_backward(self._h, _ptr(X), _ptr(E), float(nu), _ptr(dK), _ptr(dE), _ptr(dX),
+                                            _stream()), "rpim_assemble_backward")
+        return dE, dX
+
+    def status(self, raise_on_error=True):
+        bad = C.c_int64()
+        st = lib().rpim_get_status(self._h, _stream(), C.byref(bad))
+        if st != 0 and raise_on_error:
+            raise RpimError(st, "device status", f"(first bad gauss point {bad.value})")
+        return st, bad.value
+
+    def support(self):
+        torch = _torch()
+        inf = self.info()
+        gp_ptr = torch.empty(self.n_gp + 1, dtype=torch.int64, device=self.device)
+        gp_nbr = torch.empty(inf["sum_n"], dtype=torch.int32, device=self.device)
+        _check(lib().rpim_get_support(self._h, _ptr(gp_ptr), _ptr(gp_nbr), _stream()), "rpim_get_support")
+        return gp_ptr, gp_nbr
+
+    def dphi(self):
+        torch = _torch()
+        inf = self.info()
+        out = torch.empty(inf["sum_n"], 3, dtype=torch.float64, device=self.device)
+        _check(lib().rpim_get_dphi(self._h, _ptr(out), _stream()), "rpim_get_dphi")
+        return out
+
+
+def _precision(p):
+    if p in (FP64, "fp64", "f64", "double"):
+        return FP64
+    if p in (MIXED, "mixed", "fp32", "f32"):
+        return MIXED
+    raise ValueError(f"unknown precision {p!r}")
+
+
+def apply_penalty_bc(row_ptr, col_idx, K, fixed_dof, u_bar=None, factor=1e8, rhs=None):
+    """Penalty BCs in place on K (float64 or float32) and rhs; returns alpha (synchronises)."""
+    torch = _torch()
+    prec = FP64 if K.dtype == torch.float64 else MIXED
+    fx = _dev(fixed_dof, torch.int32, K.device)
+    ub = None if u_bar is None else _dev(u_bar, torch.float64, K.device)
+    alpha = C.c_double()
+    _check(lib().rpim_apply_penalty_bc(_ptr(row_ptr), _ptr(col_idx), _ptr(K), prec, int(row_ptr.numel() - 1),
+                                       _ptr(fx), _ptr(ub), int(fx.numel()), float(factor), _ptr(rhs),
+                                       C.byref(alpha), _stream()), "rpim_apply_penalty_bc")
+    return alpha.value
+
+
+def pow_cr(x, q):
+    """Correctly rounded x**q on the GPU (elementwise, float64)."""
+    torch = _torch()
+    x = x.contiguous()
+    y = torch.empty_like(x)
+    _check(lib().rpim_pow_cr(_ptr(x), float(q), _ptr(y), int(x.numel()), _stream()), "rpim_pow_cr")
+    return y
+
+
+def _make_fn():
+    torch = _torch()
+
+    class AssembleFn(torch.autograd.Function):
+        """K = assemble(node_xyz, cell_E); backward maps dL/dK to dL/dE and dL/dx."""
+
+        @staticmethod
+        def forward(ctx, node_xyz, cell_E, plan, nu, precision):
+            keep = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
+            K = plan.assemble(node_xyz.detach(), cell_E.detach(), nu, precision, keep_factors=keep)
+            ctx.plan, ctx.nu = plan, nu
+            ctx.save_for_backward(node_xyz, cell_E)
+            return K
+
+        @staticmethod
+        def backward(ctx, dK):
+            X, E = ctx.saved_tensors
+            dE, dX = ctx.plan.assemble_backward(X.detach(), E.detach(), ctx.nu, dK.detach().double().contiguous())
+            return (dX if ctx.needs_input_grad[0] else None, dE if ctx.needs_input_grad[1] else None,
+                    None, None, None)
+
+    return AssembleFn
+
+
+_AssembleFn = None
+
+
+def assemble(plan: Plan, node_xyz, cell_E, nu=0.3, precision=FP64):
+    """Differentiable stiffness assembly: K values on plan's CSR pattern."""
+    global _AssembleFn
+    if _AssembleFn is None:
+        _AssembleFn = _make_fn()
+    return _AssembleFn.apply(node_xyz, cell_E, plan, nu, precision)

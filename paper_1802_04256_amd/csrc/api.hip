@@ -1,0 +1,251 @@
+// C ABI: argument validation, plan memory, and the launch sequence of each
+// call.  Every numerical step runs in the kernels of pattern.hip,
+// assemble.hip, backward.hip and penalty.hip.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "rpim_internal.h"
+
+namespace rpim {
+
+rpim_status hip_ok(hipError_t e) {
+  if (e == hipSuccess) return RPIM_OK;
+  if (e == hipErrorOutOfMemory) return RPIM_E_NOMEM;
+  return RPIM_E_HIP;
+}
+
+namespace {
+
+template <class T>
+rpim_status dalloc(T** p, int64_t count) {
+  if (*p) return RPIM_OK;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, sizeof(T) * (size_t)count);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_ok(e);
+  }
+  return RPIM_OK;
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+rpim_status reset_status(rpim_plan* p, hipStream_t s) {
+  DevStatus clean;
+  clean.first_bad = ULLONG_MAX;
+  clean.flags = 0;
+  clean.pad = 0;
+  RPIM_HIP(hipMemcpyAsync(p->status, &clean, sizeof(DevStatus), hipMemcpyHostToDevice, s));
+  return RPIM_OK;
+}
+
+}  // namespace
+}  // namespace rpim
+
+using namespace rpim;
+
+extern "C" {
+
+const char* rpim_status_string(rpim_status st) {
+  switch (st) {
+    case RPIM_OK: return "ok";
+    case RPIM_E_ARG: return "invalid argument";
+    case RPIM_E_NOMEM: return "device allocation failed";
+    case RPIM_E_HIP: return "HIP runtime error";
+    case RPIM_E_SUPPORT: return "support has fewer than 5 nodes";
+    case RPIM_E_SINGULAR: return "singular moment matrix";
+    case RPIM_E_RANGE: return "size exceeds a documented limit";
+    case RPIM_E_POW: return "power not correctly roundable";
+    case RPIM_E_STATE: return "call order violated";
+  }
+  return "unknown status";
+}
+
+rpim_status rpim_plan_create(const rpim_problem* pb, rpim_plan** out) {
+  if (!pb || !out) return RPIM_E_ARG;
+  *out = nullptr;
+  if (pb->n_models < 1 || !pb->node_off || !pb->gp_off || !pb->support_radius || !pb->node_xyz || !pb->gp_xyz ||
+      !pb->gp_wdet || !pb->gp_cell || pb->n_cells < 1)
+    return RPIM_E_ARG;
+  if (!(pb->alpha_c > 0) || !(pb->d_c > 0) || !(pb->q > 0) || !std::isfinite(pb->alpha_c) ||
+      !std::isfinite(pb->d_c) || !std::isfinite(pb->q))
+    return RPIM_E_ARG;
+  const int M = pb->n_models;
+  if (pb->node_off[0] != 0 || pb->gp_off[0] != 0) return RPIM_E_ARG;
+  for (int m = 0; m < M; ++m) {
+    if (pb->node_off[m + 1] <= pb->node_off[m] || pb->gp_off[m + 1] < pb->gp_off[m]) return RPIM_E_ARG;
+    if (!(pb->support_radius[m] > 0) || !std::isfinite(pb->support_radius[m])) return RPIM_E_ARG;
+  }
+  const int64_t N = pb->node_off[M], G = pb->gp_off[M];
+  if (N >= INT32_MAX / 3 || G >= ((int64_t)1 << 55)) return RPIM_E_RANGE;
+  rpim_plan* p = new (std::nothrow) rpim_plan;
+  if (!p) return RPIM_E_NOMEM;
+  (void)hipGetDevice(&p->device);
+  p->n_models = M;
+  p->N = N;
+  p->G = G;
+  p->C = pb->n_cells;
+  p->alpha_c = pb->alpha_c;
+  p->d_c = pb->d_c;
+  p->q = pb->q;
+  p->node_off.assign(pb->node_off, pb->node_off + M + 1);
+  p->gp_off.assign(pb->gp_off, pb->gp_off + M + 1);
+  p->radius.assign(pb->support_radius, pb->support_radius + M);
+  rpim_status st = RPIM_OK;
+  if ((st = dalloc(&p->node_xyz0, 3 * N)) || (st = dalloc(&p->gp_xyz, 3 * G)) || (st = dalloc(&p->gp_wdet, G)) ||
+      (st = dalloc(&p->gp_cell, G)) || (st = dalloc(&p->d_gp_off, M + 1)) || (st = dalloc(&p->d_node_off, M + 1)) ||
+      (st = dalloc(&p->status, 1))) {
+    rpim_plan_destroy(p);
+    return st;
+  }
+  hipError_t e = hipMemcpy(p->node_xyz0, pb->node_xyz, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice);
+  if (G > 0) {
+    if (e == hipSuccess) e = hipMemcpy(p->gp_xyz, pb->gp_xyz, sizeof(double) * 3 * G, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->gp_wdet, pb->gp_wdet, sizeof(double) * G, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->gp_cell, pb->gp_cell, sizeof(int32_t) * G, hipMemcpyDeviceToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(p->d_gp_off, pb->gp_off, sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_node_off, pb->node_off, sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rpim_plan_destroy(p);
+    return hip_ok(e);
+  }
+  if ((st = reset_status(p, nullptr)) != RPIM_OK) {
+    rpim_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return RPIM_OK;
+}
+
+void rpim_plan_destroy(rpim_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  dfree(p->node_xyz0); dfree(p->gp_xyz); dfree(p->gp_wdet); dfree(p->gp_cell); dfree(p->d_gp_off); dfree(p->d_node_off);
+  dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
+  dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
+  dfree(p->lu_off); dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->pbar); dfree(p->dEg); dfree(p->dXs);
+  dfree(p->status);
+  delete p;
+}
+
+rpim_status rpim_build_pattern(rpim_plan* p, int64_t* row_ptr, int32_t* col_idx, int64_t* nnz, void* stream) {
+  if (!p || !nnz) return RPIM_E_ARG;
+  if ((row_ptr == nullptr) != (col_idx == nullptr)) return RPIM_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (!p->built) {
+    rpim_status st = build_pattern_device(p, p->node_xyz0, s);
+    if (st != RPIM_OK) return st;
+  }
+  *nnz = p->nnz;
+  if (row_ptr) {
+    rpim_status st = expand_pattern(p, row_ptr, col_idx, s);
+    if (st != RPIM_OK) return st;
+  }
+  return RPIM_OK;
+}
+
+rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* cell_E, double nu, int precision,
+                          int keep_factors, void* K_vals, void* stream) {
+  if (!p || !node_xyz || !cell_E || !K_vals) return RPIM_E_ARG;
+  if (!p->built) return RPIM_E_STATE;
+  if (precision != RPIM_FP64 && precision != RPIM_MIXED) return RPIM_E_ARG;
+  if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  rpim_status st;
+  if ((st = dalloc(&p->R, p->nblk)) || (st = dalloc(&p->dphi, 3 * p->sum_n))) return st;
+  if (keep_factors) {
+    if ((st = dalloc(&p->lu, p->lu_doubles)) || (st = dalloc(&p->piv, p->sum_n + 4 * p->G)) ||
+        (st = dalloc(&p->gam, 3 * (p->sum_n + 4 * p->G))))
+      return st;
+  }
+  p->have_factors = false;
+  if ((st = launch_pair_table(p, node_xyz, s)) != RPIM_OK) return st;
+  if ((st = launch_shape(p, node_xyz, keep_factors ? 1 : 0, s)) != RPIM_OK) return st;
+  if ((st = launch_rowgather(p, cell_E, nu, precision, K_vals, s)) != RPIM_OK) return st;
+  p->have_factors = keep_factors != 0;
+  return RPIM_OK;
+}
+
+rpim_status rpim_assemble_backward(rpim_plan* p, const double* node_xyz, const double* cell_E, double nu,
+                                   const double* dK_vals, double* dE_cell, double* dX_node, void* stream) {
+  if (!p || !node_xyz || !cell_E || !dK_vals || !dE_cell || !dX_node) return RPIM_E_ARG;
+  if (!p->built || !p->have_factors) return RPIM_E_STATE;
+  if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
+  return launch_backward(p, node_xyz, cell_E, nu, dK_vals, dE_cell, dX_node, (hipStream_t)stream);
+}
+
+rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, int precision,
+                                  int64_t n_dof, const int32_t* fixed_dof, const double* u_bar, int64_t n_fixed,
+                                  double factor, double* rhs, double* alpha_out, void* stream) {
+  if (!row_ptr || !col_idx || !K_vals || n_dof <= 0 || n_fixed < 0 || (n_fixed > 0 && !fixed_dof)) return RPIM_E_ARG;
+  if (precision != RPIM_FP64 && precision != RPIM_MIXED) return RPIM_E_ARG;
+  if (!(factor > 0) || !std::isfinite(factor)) return RPIM_E_ARG;
+  return launch_penalty(row_ptr, col_idx, K_vals, precision, n_dof, fixed_dof, u_bar, n_fixed, factor, rhs,
+                        alpha_out, (hipStream_t)stream);
+}
+
+rpim_status rpim_get_status(rpim_plan* p, void* stream, int64_t* first_bad_gp) {
+  if (!p) return RPIM_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  DevStatus h;
+  RPIM_HIP(hipMemcpyAsync(&h, p->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipStreamSynchronize(s));
+  rpim_status st = reset_status(p, s);
+  if (st != RPIM_OK) return st;
+  RPIM_HIP(hipStreamSynchronize(s));
+  if (first_bad_gp) *first_bad_gp = h.first_bad == ULLONG_MAX ? -1 : (int64_t)h.first_bad;
+  if (h.flags & kFlagSupport) return RPIM_E_SUPPORT;
+  if (h.flags & kFlagSingular) return RPIM_E_SINGULAR;
+  if (h.flags & kFlagRange) return RPIM_E_RANGE;
+  if (h.flags & kFlagPow) return RPIM_E_POW;
+  return RPIM_OK;
+}
+
+rpim_status rpim_plan_info(const rpim_plan* p, rpim_info* info) {
+  if (!p || !info) return RPIM_E_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->n_nodes = p->N;
+  info->n_gp = p->G;
+  info->n_cells = p->C;
+  info->n_models = p->n_models;
+  info->sum_n = p->sum_n;
+  info->nnz = p->nnz;
+  info->n_blocks = p->nblk;
+  info->min_n = p->min_n;
+  info->max_n = p->max_n;
+  info->lu_doubles = p->lu_doubles;
+  info->n_buckets = (int32_t)p->buckets.size();
+  return RPIM_OK;
+}
+
+rpim_status rpim_get_support(const rpim_plan* p, int64_t* gp_ptr, int32_t* gp_nbr, void* stream) {
+  if (!p || !gp_ptr || !gp_nbr) return RPIM_E_ARG;
+  if (!p->built) return RPIM_E_STATE;
+  hipStream_t s = (hipStream_t)stream;
+  RPIM_HIP(hipMemcpyAsync(gp_ptr, p->gp_ptr, sizeof(int64_t) * (p->G + 1), hipMemcpyDeviceToDevice, s));
+  if (p->sum_n > 0)
+    RPIM_HIP(hipMemcpyAsync(gp_nbr, p->gp_nbr, sizeof(int32_t) * p->sum_n, hipMemcpyDeviceToDevice, s));
+  return RPIM_OK;
+}
+
+rpim_status rpim_get_dphi(const rpim_plan* p, double* dphi, void* stream) {
+  if (!p || !dphi) return RPIM_E_ARG;
+  if (!p->dphi) return RPIM_E_STATE;
+  RPIM_HIP(hipMemcpyAsync(dphi, p->dphi, sizeof(double) * 3 * p->sum_n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return RPIM_OK;
+}
+
+rpim_status rpim_pow_cr(const double* x, double q, double* y, int64_t n, void* stream) {
+  if ((!x || !y) && n > 0) return RPIM_E_ARG;
+  if (n < 0 || !(q > 0)) return RPIM_E_ARG;
+  return launch_pow_test(x, q, y, n, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,356 @@
+// Stage 1 forward: radial-basis pair table, per-point moment-matrix solve,
+// and the deterministic row-gather reduction of B^T D B into K.
+//
+// Arithmetic follows one fixed operation order (shared with the CPU checker
+// as a written contract, not as code):
+//   s   = fma(dz,dz, fma(dy,dy, dx*dx)),  d = x_a - x_b
+//   R   = correctly rounded (fl(s + C^2))^q                   (dd_pow.h)
+//   rhs = fl(fl(2q) * R) / t * fl(x_g - x_a)_k,  t = fl(s_ag + C^2)
+//   LU  : pivot = first largest |a_rk| in current row order, whole-row swap,
+//         l = a_rk / a_kk (IEEE), a_rj = fma(-l, a_kj, a_rj); right-hand
+//         sides eliminated as extra columns; back substitution k descending.
+//   k_IJ: e = fma(lc, m1, mc*m2), m1 = pI_al pJ_be, m2 = pI_be pJ_al (+ dot),
+//         dot = fma(pI2,pJ2, fma(pI1,pJ1, pI0 pJ0)).
+//   K   : +0 + e_g1 + e_g2 + ... over contributing points in ascending g.
+#include <cfloat>
+
+#include "dd_pow.h"
+#include "rpim_internal.h"
+
+namespace rpim {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ void flag_error(DevStatus* st, unsigned flag, int64_t g) {
+  atomicOr(&st->flags, flag);
+  if (g >= 0) atomicMin(&st->first_bad, (unsigned long long)g);
+}
+
+__device__ __forceinline__ double sqdist(const double* a, const double* b) {
+  const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+  return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+}
+
+// ---- radial basis on every node pair of the pattern -------------------------
+__global__ void k_pair_table(int64_t nblk, const int32_t* blk_row, const int32_t* blk_col, const double* X,
+                             double C2, double q, double* R, DevStatus* st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nblk) return;
+  const int64_t I = blk_row[e], J = blk_col[e];
+  const double t = sqdist(X + 3 * I, X + 3 * J) + C2;
+  bool hard = false;
+  R[e] = pow_cr(t, q, &hard);
+  if (hard) flag_error(st, kFlagPow, -1);
+}
+
+__global__ void k_pow_test(const double* x, double q, double* y, int64_t n, DevStatus* st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool hard = false;
+  y[i] = pow_cr(x[i], q, &hard);
+  if (hard && st) flag_error(st, kFlagPow, -1);
+}
+
+// First index of `key` in the sorted range [b, e) (the caller guarantees presence).
+__device__ __forceinline__ int64_t find_sorted(const int32_t* v, int64_t b, int64_t e, int32_t key) {
+  while (b < e) {
+    const int64_t m = (b + e) >> 1;
+    if (v[m] < key) b = m + 1; else e = m;
+  }
+  return b;
+}
+
+// Block-wide argmax of (value, row) with ties to the smaller row.
+__device__ __forceinline__ void argmax_pair(double v, int r, double* sv, int* sr, double* out_v, int* out_r) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v2 = __shfl_xor(v, o, 64);
+    const int r2 = __shfl_xor(r, o, 64);
+    if (v2 > v || (v2 == v && r2 < r)) { v = v2; r = r2; }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sv[w] = v; sr[w] = r; }
+  __syncthreads();
+  double bv = sv[0];
+  int br = sr[0];
+  for (int i = 1; i < kThreads / 64; ++i)
+    if (sv[i] > bv || (sv[i] == bv && sr[i] < br)) { bv = sv[i]; br = sr[i]; }
+  *out_v = bv;
+  *out_r = br;
+  __syncthreads();
+}
+
+// ---- one workgroup per Gauss point: moment matrix, LU, three solves --------
+// LDS: A[N][ld] (augmented with 3 right-hand sides), S[n], pivots[N].
+__global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int64_t order_begin,
+                                                    const int64_t* gp_ptr, const int32_t* gp_nbr,
+                                                    const int64_t* blk_ptr, const int32_t* blk_col, const double* R,
+                                                    const double* X, const double* gp_xyz, double C2, double q,
+                                                    int ld, double* dphi, int keep, const int64_t* lu_off,
+                                                    double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
+  extern __shared__ double smem[];
+  __shared__ double red_v[kThreads / 64];
+  __shared__ int red_r[kThreads / 64];
+  __shared__ double xg[3];
+  const int tid = threadIdx.x;
+  const int64_t g = gp_order[order_begin + blockIdx.x];
+  const int64_t b0 = gp_ptr[g];
+  const int n = (int)(gp_ptr[g + 1] - b0);
+  const int N = n + 4, W = N + 3;
+  double* A = smem;
+  int* S = (int*)(A + (size_t)N * ld);
+  int* pv = S + n;
+  for (int i = tid; i < n; i += kThreads) S[i] = gp_nbr[b0 + i];
+  for (int i = tid; i < N * ld; i += kThreads) A[i] = 0.0;
+  if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
+  __syncthreads();
+
+  // R block from the pair table: G[a][b] = G[b][a] = R(S[a], S[b]), a <= b
+  for (int idx = tid; idx < n * n; idx += kThreads) {
+    const int a = idx / n, b = idx - a * n;
+    if (b < a) continue;
+    const int32_t I = S[a];
+    const int64_t pos = find_sorted(blk_col, blk_ptr[I], blk_ptr[I + 1], S[b]);
+    const double v = R[pos];
+    A[a * ld + b] = v;
+    A[b * ld + a] = v;
+  }
+  // polynomial block and right-hand sides
+  const double two_q = 2.0 * q;
+  for (int a = tid; a < n; a += kThreads) {
+    const double* xa = X + 3 * (int64_t)S[a];
+    A[a * ld + n] = 1.0;
+    A[n * ld + a] = 1.0;
+    for (int k = 0; k < 3; ++k) {
+      const double d = xa[k] - xg[k];
+      A[a * ld + n + 1 + k] = d;
+      A[(n + 1 + k) * ld + a] = d;
+    }
+    const double t = sqdist(xa, xg) + C2;
+    bool hard = false;
+    const double Rv = pow_cr(t, q, &hard);
+    if (hard) flag_error(st, kFlagPow, g);
+    const double coef = (two_q * Rv) / t;
+    for (int k = 0; k < 3; ++k) A[a * ld + N + k] = coef * (xg[k] - xa[k]);
+  }
+  if (tid < 3) A[(n + 1 + tid) * ld + N + tid] = 1.0;
+  __syncthreads();
+
+  // singularity threshold N * eps * max|G|
+  double mx = 0.0;
+  for (int idx = tid; idx < N * N; idx += kThreads) {
+    const int r = idx / N, c = idx - r * N;
+    mx = fmax(mx, fabs(A[r * ld + c]));
+  }
+  double maxabs;
+  int dummy;
+  argmax_pair(mx, 0, red_v, red_r, &maxabs, &dummy);
+  const double tiny = ((double)N * DBL_EPSILON) * maxabs;
+
+  bool singular = false;
+  for (int k = 0; k < N; ++k) {
+    double v = -1.0;
+    int r = N;
+    for (int i = k + tid; i < N; i += kThreads) {
+      const double a = fabs(A[i * ld + k]);
+      if (a > v) { v = a; r = i; }
+    }
+    double best;
+    int p;
+    argmax_pair(v, r, red_v, red_r, &best, &p);
+    if (!(best > tiny)) { singular = true; break; }
+    if (tid == 0) pv[k] = p;
+    if (p != k)
+      for (int c = tid; c < W; c += kThreads) {
+        const double t = A[k * ld + c];
+        A[k * ld + c] = A[p * ld + c];
+        A[p * ld + c] = t;
+      }
+    __syncthreads();
+    const double piv = A[k * ld + k];
+    for (int i = k + 1 + tid; i < N; i += kThreads) A[i * ld + k] = A[i * ld + k] / piv;
+    __syncthreads();
+    const int m = N - k - 1, wc = W - k - 1;
+    for (int idx = tid; idx < m * wc; idx += kThreads) {
+      const int i = k + 1 + idx / wc, c = k + 1 + idx % wc;
+      A[i * ld + c] = __builtin_fma(-A[i * ld + k], A[k * ld + c], A[i * ld + c]);
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    if (tid == 0) flag_error(st, kFlagSingular, g);
+    return;
+  }
+  // back substitution on the three right-hand sides
+  for (int k = N - 1; k >= 0; --k) {
+    if (tid < 3) A[k * ld + N + tid] = A[k * ld + N + tid] / A[k * ld + k];
+    __syncthreads();
+    for (int idx = tid; idx < 3 * k; idx += kThreads) {
+      const int i = idx / 3, j = idx - 3 * i;
+      A[i * ld + N + j] = __builtin_fma(-A[i * ld + k], A[k * ld + N + j], A[i * ld + N + j]);
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < 3 * n; idx += kThreads) {
+    const int a = idx / 3, k = idx - 3 * a;
+    dphi[3 * (b0 + a) + k] = A[a * ld + N + k];
+  }
+  if (keep) {
+    double* L = lu + lu_off[g];
+    for (int idx = tid; idx < N * N; idx += kThreads) {
+      const int r = idx / N, c = idx - r * N;
+      L[idx] = A[r * ld + c];
+    }
+    const int64_t o = b0 + 4 * g;
+    for (int i = tid; i < N; i += kThreads) piv_out[o + i] = pv[i];
+    for (int idx = tid; idx < 3 * N; idx += kThreads) {
+      const int k = idx / N, i = idx - k * N;
+      gam[3 * o + idx] = A[i * ld + N + k];
+    }
+  }
+}
+
+// ---- row gather: one workgroup per node row I --------------------------------
+// acc[pos][9] over the row's column blocks; contributions arrive in ascending g.
+template <bool kMixed>
+__global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
+                                                        const int64_t* inv_ptr, const uint64_t* inv_key,
+                                                        const int64_t* gp_ptr, const int32_t* gp_nbr,
+                                                        const double* dphi, const double* wdet,
+                                                        const int32_t* gp_cell, const double* E, double lam,
+                                                        double mu, void* Kout) {
+  extern __shared__ double smem[];
+  const int64_t I = blockIdx.x;
+  const int64_t rb = blk_ptr[I];
+  const int L = (int)(blk_ptr[I + 1] - rb);
+  double* acc = smem;                       // [L][9] FP64, or [L][9] float2 (sum, compensation)
+  int32_t* cols = (int32_t*)(acc + 9 * L);  // [L]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < L; i += kThreads) cols[i] = blk_col[rb + i];
+  for (int i = tid; i < 9 * L; i += kThreads) acc[i] = 0.0;
+  __syncthreads();
+  for (int64_t e = inv_ptr[I]; e < inv_ptr[I + 1]; ++e) {
+    const uint64_t key = inv_key[e];
+    const int64_t g = (int64_t)(key >> 8);
+    const int aI = (int)(key & 255);
+    const int64_t b0 = gp_ptr[g];
+    const int n = (int)(gp_ptr[g + 1] - b0);
+    const double c = wdet[g] * E[gp_cell[g]];
+    const double lc = c * lam, mc = c * mu;
+    const double pI0 = dphi[3 * (b0 + aI)], pI1 = dphi[3 * (b0 + aI) + 1], pI2 = dphi[3 * (b0 + aI) + 2];
+    for (int item = tid; item < 3 * n; item += kThreads) {
+      const int b = item / 3, al = item - 3 * b;
+      const int32_t J = gp_nbr[b0 + b];
+      const double pJ0 = dphi[3 * (b0 + b)], pJ1 = dphi[3 * (b0 + b) + 1], pJ2 = dphi[3 * (b0 + b) + 2];
+      int lo = 0, hi = L;
+      while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (cols[m] < J) lo = m + 1; else hi = m;
+      }
+      const double pI[3] = {pI0, pI1, pI2}, pJ[3] = {pJ0, pJ1, pJ2};
+      if (!kMixed) {
+        const double dot = __builtin_fma(pI2, pJ2, __builtin_fma(pI1, pJ1, pI0 * pJ0));
+        double* a = acc + 9 * lo + 3 * al;
+        for (int be = 0; be < 3; ++be) {
+          const double m1 = pI[al] * pJ[be];
+          double m2 = pI[be] * pJ[al];
+          if (al == be) m2 = m2 + dot;
+          a[be] = a[be] + __builtin_fma(lc, m1, mc * m2);
+        }
+      } else {
+        const float fI[3] = {(float)pI0, (float)pI1, (float)pI2}, fJ[3] = {(float)pJ0, (float)pJ1, (float)pJ2};
+        const float flc = (float)lc, fmc = (float)mc;
+        const float dot = __builtin_fmaf(fI[2], fJ[2], __builtin_fmaf(fI[1], fJ[1], fI[0] * fJ[0]));
+        float2* a = reinterpret_cast<float2*>(acc) + 9 * lo + 3 * al;
+        for (int be = 0; be < 3; ++be) {
+          const float m1 = fI[al] * fJ[be];
+          float m2 = fI[be] * fJ[al];
+          if (al == be) m2 = m2 + dot;
+          const float ev = __builtin_fmaf(flc, m1, fmc * m2);
+          float2 sc = a[be];
+          const float y = ev - sc.y;
+          const float t = sc.x + y;
+          sc.y = (t - sc.x) - y;
+          sc.x = t;
+          a[be] = sc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t base = 9 * rb;
+  for (int idx = tid; idx < 9 * L; idx += kThreads) {
+    const int pos = idx / 9, r = idx - 9 * pos, al = r / 3, be = r - 3 * al;
+    const int64_t o = base + 3 * (int64_t)al * L + 3 * pos + be;
+    if (!kMixed) ((double*)Kout)[o] = acc[idx];
+    else ((float*)Kout)[o] = reinterpret_cast<float2*>(acc)[idx].x;
+  }
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s) {
+  const double ac = p->alpha_c * p->d_c;
+  const double C2 = ac * ac;
+  if (p->nblk == 0) return RPIM_OK;
+  hipLaunchKernelGGL(k_pair_table, dim3(nblocks(p->nblk, 256)), dim3(256), 0, s, p->nblk,
+                     (const int32_t*)p->blk_row, (const int32_t*)p->blk_col, X, C2, p->q, p->R, p->status);
+  RPIM_HIP(hipGetLastError());
+  return RPIM_OK;
+}
+
+rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s) {
+  const double ac = p->alpha_c * p->d_c;
+  const double C2 = ac * ac;
+  for (const Bucket& b : p->buckets) {
+    const int N = b.nmax;
+    const int ld = ((N + 3) | 1);  // odd row stride in doubles
+    const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
+    if (lds > 160 * 1024) return RPIM_E_RANGE;
+    RPIM_HIP(hipFuncSetAttribute((const void*)k_shape, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
+                       b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
+                       (const int32_t*)p->blk_col, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
+                       p->dphi, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
+    RPIM_HIP(hipGetLastError());
+  }
+  return RPIM_OK;
+}
+
+rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s) {
+  const double onep = 1.0 + nu;
+  const double onem = 1.0 - 2.0 * nu;
+  const double lam = nu / (onep * onem);
+  const double mu = 1.0 / (2.0 * onep);
+  const int L = (int)p->max_row_blocks;
+  const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(int32_t) * (size_t)L;
+  if (lds > 160 * 1024) return RPIM_E_RANGE;
+  if (precision == RPIM_FP64) {
+    RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
+                       (const int32_t*)p->blk_col, (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
+                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
+                       (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
+  } else {
+    RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
+                       (const int32_t*)p->blk_col, (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
+                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
+                       (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
+  }
+  RPIM_HIP(hipGetLastError());
+  return RPIM_OK;
+}
+
+rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return RPIM_OK;
+  hipLaunchKernelGGL(k_pow_test, dim3(nblocks(n, 256)), dim3(256), 0, s, x, q, y, n, (DevStatus*)nullptr);
+  RPIM_HIP(hipGetLastError());
+  return RPIM_OK;
+}
+
+}  // namespace rpim

@@ -1,0 +1,132 @@
+// Internal state and launcher declarations of the RPIM library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/rpim.h"
+
+namespace rpim {
+
+// Limits (documented in rpim.h).
+constexpr int kMaxSupport = 256;        // nodes per support
+constexpr int kMaxInverse = 8192;       // supports containing one node
+constexpr int64_t kMaxWindow = 1 << 18; // node-id span of a node's neighbourhood
+
+// Device-side error record: smallest failing Gauss point and kinds seen.
+struct DevStatus {
+  unsigned long long first_bad;  // ULLONG_MAX when clean
+  unsigned int flags;            // bit set of kFlag*
+  unsigned int pad;
+};
+constexpr unsigned kFlagSupport = 1u, kFlagSingular = 2u, kFlagPow = 4u, kFlagRange = 8u;
+
+// Uniform bin grid of one model for the support search.
+struct BinGrid {
+  double ox, oy, oz;  // origin
+  double h;           // bin edge (>= support radius)
+  double r2;          // fl(d_s * d_s)
+  int nx, ny, nz;     // bins per axis
+  int pad;
+  int64_t bin0;       // first global bin id of this model
+};
+
+// Gauss points with the same padded moment-matrix size share a bucket.
+struct Bucket {
+  int nmax;        // largest N = n + 4 in the bucket
+  int64_t begin;   // range in gp_order
+  int64_t count;
+};
+
+}  // namespace rpim
+
+struct rpim_plan {
+  int device = 0;
+  int32_t n_models = 0;
+  int64_t N = 0, G = 0, C = 0;
+  double alpha_c = 0, d_c = 0, q = 0;
+  std::vector<int64_t> node_off, gp_off;
+  std::vector<double> radius;
+
+  // plan-owned device copies of the Gauss-point description
+  double* node_xyz0 = nullptr;   // [N][3] build-time node coordinates
+  double* gp_xyz = nullptr;
+  double* gp_wdet = nullptr;
+  int32_t* gp_cell = nullptr;
+  int64_t* d_gp_off = nullptr;   // [n_models+1]
+  int64_t* d_node_off = nullptr; // [n_models+1]
+
+  // pattern (built by rpim_build_pattern)
+  bool built = false;
+  int64_t sum_n = 0, nblk = 0, nnz = 0;
+  int32_t min_n = 0, max_n = 0;
+  int64_t* gp_ptr = nullptr;     // [G+1]
+  int32_t* gp_nbr = nullptr;     // [sum_n]
+  int64_t* inv_ptr = nullptr;    // [N+1]
+  uint64_t* inv_key = nullptr;   // [sum_n]  (g << 8) | local index, ascending g per node
+  int64_t* blk_ptr = nullptr;    // [N+1]
+  int32_t* blk_col = nullptr;    // [nblk]
+  int32_t* blk_row = nullptr;    // [nblk]
+  int64_t max_row_blocks = 0;    // longest node-block row
+  int64_t max_inverse = 0;       // longest inverse list
+  std::vector<rpim::Bucket> buckets;
+  int32_t* gp_order = nullptr;   // [G] Gauss points grouped by bucket
+
+  // assembly workspace
+  double* R = nullptr;           // [nblk] radial basis per node pair
+  double* dphi = nullptr;        // [sum_n][3]
+  float* dphi32 = nullptr;       // [sum_n][3] (mixed precision)
+
+  // kept factors (keep_factors = 1)
+  int64_t* lu_off = nullptr;     // [G+1] offsets in doubles: N_g * N_g per point
+  int64_t lu_doubles = 0;
+  double* lu = nullptr;          // [lu_doubles] rows in pivoted order
+  int32_t* piv = nullptr;        // [sum_n + 4G] pivot rows, per point at 4g + gp_ptr[g]
+  double* gam = nullptr;         // [3 * (sum_n + 4G)] full solutions gamma_k per point
+  bool have_factors = false;
+
+  // backward scratch
+  double* pbar = nullptr;        // [sum_n][3]   dL/dphi per support entry
+  double* dEg = nullptr;         // [G]          dL/dE contribution per Gauss point
+  double* dXs = nullptr;         // [sum_n][3]   dL/dx contribution per support entry
+
+  rpim::DevStatus* status = nullptr;
+};
+
+namespace rpim {
+
+// --- helpers (api.cpp) -----------------------------------------------------
+rpim_status hip_ok(hipError_t e);
+#define RPIM_HIP(x)                                 \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return rpim::hip_ok(e_);  \
+  } while (0)
+
+// --- scan.hip ----------------------------------------------------------------
+// Exclusive prefix sum of n int32 counts into int64 offsets out[n+1].
+rpim_status exclusive_scan(const int32_t* counts, int64_t n, int64_t* out, hipStream_t s);
+
+// --- pattern.hip -------------------------------------------------------------
+rpim_status build_pattern_device(rpim_plan* p, const double* node_xyz, hipStream_t s);
+rpim_status expand_pattern(const rpim_plan* p, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
+
+// --- assemble.hip ------------------------------------------------------------
+rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s);
+rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s);
+rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K,
+                             hipStream_t s);
+rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s);
+
+// --- backward.hip ------------------------------------------------------------
+rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, double nu,
+                            const double* dK, double* dE, double* dX, hipStream_t s);
+
+// --- penalty.hip -------------------------------------------------------------
+rpim_status launch_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision,
+                           int64_t n_dof, const int32_t* fixed, const double* ubar, int64_t n_fixed,
+                           double factor, double* rhs, double* alpha_out, hipStream_t s);
+
+}  // namespace rpim
