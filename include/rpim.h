@@ -80,6 +80,19 @@ typedef struct {
 
 typedef struct rpim_plan rpim_plan; /* opaque; owns device memory for supports etc. */
 
+/* Phases reported by rpim_profile_read (milliseconds of the most recent call
+ * that ran the phase, from HIP events recorded on that call's stream). */
+enum {
+  RPIM_PHASE_PATTERN = 0,    /* support search + pattern (build or rebuild)        */
+  RPIM_PHASE_PAIRS = 1,      /* radial basis on node pairs                         */
+  RPIM_PHASE_SHAPE = 2,      /* moment matrices, LU, solves (all buckets)          */
+  RPIM_PHASE_GATHER = 3,     /* B^T D B reduction into K                           */
+  RPIM_PHASE_BWD_ROWS = 4,   /* adjoint: symmetrise dK + row gather                */
+  RPIM_PHASE_BWD_GP = 5,     /* adjoint: per-point solves and chain rule           */
+  RPIM_PHASE_BWD_REDUCE = 6, /* adjoint: slot reductions to nodes and cells        */
+  RPIM_N_PHASES = 7
+};
+
 /* Sizes of a built plan (filled by rpim_plan_info). */
 typedef struct {
   int64_t n_nodes, n_gp, n_cells, n_models;
@@ -111,6 +124,14 @@ rpim_status rpim_plan_create(const rpim_problem* problem, rpim_plan** plan);
  * supports, or the node ids in a node's neighbourhood span more than 2^18. */
 rpim_status rpim_build_pattern(rpim_plan* plan, int64_t* row_ptr, int32_t* col_idx, int64_t* nnz,
                                void* stream);
+
+/* Re-run the support search and pattern for new node coordinates node_xyz
+ * [N][3] (e.g. after the nodes have moved), replacing the plan's supports and
+ * pattern and keeping its workspaces where they are large enough.  Same
+ * contract, limits and synchronisation as rpim_build_pattern; kept LU factors
+ * are invalidated. */
+rpim_status rpim_rebuild_pattern(rpim_plan* plan, const double* node_xyz, int64_t* row_ptr, int32_t* col_idx,
+                                 int64_t* nnz, void* stream);
 
 /* Stage 1, forward (asynchronous).  node_xyz [N][3] may differ from the
  * build-time coordinates: supports and pattern stay frozen.  cell_E [n_cells],
@@ -149,6 +170,13 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
 rpim_status rpim_get_status(rpim_plan* plan, void* stream, int64_t* first_bad_gp);
 
 rpim_status rpim_plan_info(const rpim_plan* plan, rpim_info* info);
+
+/* Enable (1) or disable (0) per-phase event timing for later calls on this
+ * plan; rpim_profile_read synchronises on the recorded events and writes
+ * RPIM_N_PHASES values in milliseconds to ms (host), -1 for phases not run
+ * since timing was enabled. */
+rpim_status rpim_profile_enable(rpim_plan* plan, int enable);
+rpim_status rpim_profile_read(rpim_plan* plan, double* ms);
 
 /* Copies of plan state for inspection and tests (device outputs, async):
  * supports gp_ptr int64[G+1], gp_nbr int32[sum_n]; shape-function gradients

@@ -67,12 +67,16 @@ def lib():
         L.rpim_get_support.argtypes = [vp, vp, vp, vp]
         L.rpim_get_dphi.argtypes = [vp, vp, vp]
         L.rpim_pow_cr.argtypes = [vp, d, vp, i64, vp]
+        L.rpim_rebuild_pattern.argtypes = [vp, vp, vp, vp, C.POINTER(i64), vp]
+        L.rpim_profile_enable.argtypes = [vp, i32]
+        L.rpim_profile_read.argtypes = [vp, C.POINTER(d)]
         L.rpim_plan_destroy.argtypes = [vp]
         L.rpim_plan_destroy.restype = None
         L.rpim_status_string.restype = C.c_char_p
         for f in ("rpim_plan_create", "rpim_build_pattern", "rpim_assemble", "rpim_assemble_backward",
                   "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
-                  "rpim_get_dphi", "rpim_pow_cr"):
+                  "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
+                  "rpim_profile_read"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -170,6 +174,31 @@ class Plan:
         _check(lib().rpim_build_pattern(self._h, _ptr(self.row_ptr), _ptr(self.col_idx), C.byref(nnz), _stream()),
                "rpim_build_pattern")
         return self.row_ptr, self.col_idx
+
+    def rebuild_pattern(self, node_xyz):
+        """Re-run support search and pattern for moved nodes (synchronous)."""
+        torch = _torch()
+        X = _dev(node_xyz, torch.float64, self.device)
+        nnz = C.c_int64()
+        _check(lib().rpim_rebuild_pattern(self._h, _ptr(X), None, None, C.byref(nnz), _stream()),
+               "rpim_rebuild_pattern")
+        if nnz.value != self.nnz:
+            self.nnz = nnz.value
+            self.col_idx = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        _check(lib().rpim_build_pattern(self._h, _ptr(self.row_ptr), _ptr(self.col_idx), C.byref(nnz), _stream()),
+               "rpim_build_pattern")
+        self.node_xyz = X
+        return self.row_ptr, self.col_idx
+
+    PHASES = ("pattern", "pairs", "shape", "gather", "bwd_rows", "bwd_gp", "bwd_reduce")
+
+    def profile(self, enable: bool = True):
+        _check(lib().rpim_profile_enable(self._h, int(bool(enable))), "rpim_profile_enable")
+
+    def profile_read(self) -> dict:
+        out = (C.c_double * len(self.PHASES))()
+        _check(lib().rpim_profile_read(self._h, out), "rpim_profile_read")
+        return {k: out[i] for i, k in enumerate(self.PHASES) if out[i] >= 0}
 
     def info(self) -> dict:
         inf = _Info()

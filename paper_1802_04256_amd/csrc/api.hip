@@ -16,6 +16,39 @@ rpim_status hip_ok(hipError_t e) {
   return RPIM_E_HIP;
 }
 
+rpim_status ensure_alloc(void** p, int64_t* cap, int64_t count, size_t elem) {
+  if (count <= 0) count = 1;
+  if (*p && *cap >= count) return RPIM_OK;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (e != hipSuccess) return hip_ok(e);
+  }
+  hipError_t e = hipMalloc(p, elem * (size_t)count);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_ok(e);
+  }
+  *cap = count;
+  return RPIM_OK;
+}
+
+void phase_begin(rpim_plan* p, int phase, hipStream_t s) {
+  if (!p->profiling) return;
+  if (!p->ev[2 * phase]) {
+    (void)hipEventCreate(&p->ev[2 * phase]);
+    (void)hipEventCreate(&p->ev[2 * phase + 1]);
+  }
+  (void)hipEventRecord(p->ev[2 * phase], s);
+}
+
+void phase_end(rpim_plan* p, int phase, hipStream_t s) {
+  if (!p->profiling || !p->ev[2 * phase]) return;
+  (void)hipEventRecord(p->ev[2 * phase + 1], s);
+  p->phase_recorded[phase] = true;
+}
+
 namespace {
 
 template <class T>
@@ -130,8 +163,11 @@ void rpim_plan_destroy(rpim_plan* p) {
   dfree(p->node_xyz0); dfree(p->gp_xyz); dfree(p->gp_wdet); dfree(p->gp_cell); dfree(p->d_gp_off); dfree(p->d_node_off);
   dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
   dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
-  dfree(p->lu_off); dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->pbar); dfree(p->dEg); dfree(p->dXs);
+  dfree(p->lu_off); dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->msym); dfree(p->pbar); dfree(p->dEs); dfree(p->dEg); dfree(p->dXs);
+  dfree(p->cell_ptr); dfree(p->cell_gp);
   dfree(p->status);
+  for (int i = 0; i < 2 * RPIM_N_PHASES; ++i)
+    if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
   delete p;
 }
 
@@ -140,13 +176,51 @@ rpim_status rpim_build_pattern(rpim_plan* p, int64_t* row_ptr, int32_t* col_idx,
   if ((row_ptr == nullptr) != (col_idx == nullptr)) return RPIM_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   if (!p->built) {
+    phase_begin(p, RPIM_PHASE_PATTERN, s);
     rpim_status st = build_pattern_device(p, p->node_xyz0, s);
+    phase_end(p, RPIM_PHASE_PATTERN, s);
     if (st != RPIM_OK) return st;
   }
   *nnz = p->nnz;
   if (row_ptr) {
     rpim_status st = expand_pattern(p, row_ptr, col_idx, s);
     if (st != RPIM_OK) return st;
+  }
+  return RPIM_OK;
+}
+
+rpim_status rpim_rebuild_pattern(rpim_plan* p, const double* node_xyz, int64_t* row_ptr, int32_t* col_idx,
+                                 int64_t* nnz, void* stream) {
+  if (!p || !node_xyz || !nnz) return RPIM_E_ARG;
+  if ((row_ptr == nullptr) != (col_idx == nullptr)) return RPIM_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  RPIM_HIP(hipStreamSynchronize(s));
+  dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
+  dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->lu_off);
+  dfree(p->cell_ptr); dfree(p->cell_gp);
+  p->built = false;
+  p->have_factors = false;
+  p->buckets.clear();
+  RPIM_HIP(hipMemcpyAsync(p->node_xyz0, node_xyz, sizeof(double) * 3 * p->N, hipMemcpyDeviceToDevice, s));
+  return rpim_build_pattern(p, row_ptr, col_idx, nnz, stream);
+}
+
+rpim_status rpim_profile_enable(rpim_plan* p, int enable) {
+  if (!p) return RPIM_E_ARG;
+  p->profiling = enable != 0;
+  for (int i = 0; i < RPIM_N_PHASES; ++i) p->phase_recorded[i] = false;
+  return RPIM_OK;
+}
+
+rpim_status rpim_profile_read(rpim_plan* p, double* ms) {
+  if (!p || !ms) return RPIM_E_ARG;
+  for (int i = 0; i < RPIM_N_PHASES; ++i) {
+    ms[i] = -1.0;
+    if (!p->phase_recorded[i]) continue;
+    RPIM_HIP(hipEventSynchronize(p->ev[2 * i + 1]));
+    float t = 0.f;
+    RPIM_HIP(hipEventElapsedTime(&t, p->ev[2 * i], p->ev[2 * i + 1]));
+    ms[i] = t;
   }
   return RPIM_OK;
 }
@@ -159,16 +233,22 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
   if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   rpim_status st;
-  if ((st = dalloc(&p->R, p->nblk)) || (st = dalloc(&p->dphi, 3 * p->sum_n))) return st;
+  if ((st = ensure(&p->R, &p->cap_R, p->nblk)) || (st = ensure(&p->dphi, &p->cap_dphi, 3 * p->sum_n))) return st;
   if (keep_factors) {
-    if ((st = dalloc(&p->lu, p->lu_doubles)) || (st = dalloc(&p->piv, p->sum_n + 4 * p->G)) ||
-        (st = dalloc(&p->gam, 3 * (p->sum_n + 4 * p->G))))
+    if ((st = ensure(&p->lu, &p->cap_lu, p->lu_doubles)) || (st = ensure(&p->piv, &p->cap_piv, p->sum_n + 4 * p->G)) ||
+        (st = ensure(&p->gam, &p->cap_gam, 3 * (p->sum_n + 4 * p->G))))
       return st;
   }
   p->have_factors = false;
+  phase_begin(p, RPIM_PHASE_PAIRS, s);
   if ((st = launch_pair_table(p, node_xyz, s)) != RPIM_OK) return st;
+  phase_end(p, RPIM_PHASE_PAIRS, s);
+  phase_begin(p, RPIM_PHASE_SHAPE, s);
   if ((st = launch_shape(p, node_xyz, keep_factors ? 1 : 0, s)) != RPIM_OK) return st;
+  phase_end(p, RPIM_PHASE_SHAPE, s);
+  phase_begin(p, RPIM_PHASE_GATHER, s);
   if ((st = launch_rowgather(p, cell_E, nu, precision, K_vals, s)) != RPIM_OK) return st;
+  phase_end(p, RPIM_PHASE_GATHER, s);
   p->have_factors = keep_factors != 0;
   return RPIM_OK;
 }

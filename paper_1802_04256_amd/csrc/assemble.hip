@@ -196,9 +196,9 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
     dphi[3 * (b0 + a) + k] = A[a * ld + N + k];
   }
   if (keep) {
-    double* L = lu + lu_off[g];
+    double* L = lu + lu_off[g];  // column-major: the adjoint solves walk columns
     for (int idx = tid; idx < N * N; idx += kThreads) {
-      const int r = idx / N, c = idx - r * N;
+      const int c = idx / N, r = idx - c * N;
       L[idx] = A[r * ld + c];
     }
     const int64_t o = b0 + 4 * g;

@@ -498,6 +498,26 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   }
   RPIM_HIP(hipMalloc((void**)&p->gp_order, sizeof(int32_t) * std::max<int64_t>(G, 1)));
   RPIM_HIP(hipMemcpyAsync(p->gp_order, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+  // cell -> Gauss point lists (ascending g) for the deterministic dE reduction
+  {
+    std::vector<int32_t> cell_h(G);
+    RPIM_HIP(hipMemcpyAsync(cell_h.data(), p->gp_cell, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+    RPIM_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> cptr(p->C + 1, 0);
+    for (int64_t g = 0; g < G; ++g) {
+      if (cell_h[g] < 0 || cell_h[g] >= p->C) return RPIM_E_ARG;
+      cptr[cell_h[g] + 1]++;
+    }
+    for (int64_t c = 0; c < p->C; ++c) cptr[c + 1] += cptr[c];
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    std::vector<int32_t> cgp(std::max<int64_t>(G, 1));
+    for (int64_t g = 0; g < G; ++g) cgp[fill[cell_h[g]]++] = (int32_t)g;
+    RPIM_HIP(hipMalloc((void**)&p->cell_ptr, sizeof(int64_t) * (p->C + 1)));
+    RPIM_HIP(hipMalloc((void**)&p->cell_gp, sizeof(int32_t) * std::max<int64_t>(G, 1)));
+    RPIM_HIP(hipMemcpyAsync(p->cell_ptr, cptr.data(), sizeof(int64_t) * (p->C + 1), hipMemcpyHostToDevice, s));
+    RPIM_HIP(hipMemcpyAsync(p->cell_gp, cgp.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
+    RPIM_HIP(hipStreamSynchronize(s));
+  }
   RPIM_HIP(hipMalloc((void**)&p->lu_off, sizeof(int64_t) * (G + 1)));
   RPIM_HIP(hipMemcpyAsync(p->lu_off, lu_off_h.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   RPIM_HIP(hipStreamSynchronize(s));

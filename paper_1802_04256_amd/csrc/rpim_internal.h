@@ -87,18 +87,42 @@ struct rpim_plan {
   double* gam = nullptr;         // [3 * (sum_n + 4G)] full solutions gamma_k per point
   bool have_factors = false;
 
-  // backward scratch
+  // backward scratch and cell -> Gauss point lists
+  double* msym = nullptr;        // [nnz]        dK + dK^T on the pattern
   double* pbar = nullptr;        // [sum_n][3]   dL/dphi per support entry
+  double* dEs = nullptr;         // [sum_n]      dL/dE share per support entry (row of the entry)
   double* dEg = nullptr;         // [G]          dL/dE contribution per Gauss point
   double* dXs = nullptr;         // [sum_n][3]   dL/dx contribution per support entry
+  int64_t* cell_ptr = nullptr;   // [C+1]
+  int32_t* cell_gp = nullptr;    // [G] Gauss points of each cell, ascending
 
   rpim::DevStatus* status = nullptr;
+
+  // capacities (elements) of the workspaces above, so a rebuilt pattern can reuse them
+  int64_t cap_R = 0, cap_dphi = 0, cap_lu = 0, cap_piv = 0, cap_gam = 0;
+  int64_t cap_msym = 0, cap_pbar = 0, cap_dEs = 0, cap_dEg = 0, cap_dXs = 0;
+
+  // optional per-phase timing with HIP events on the call's stream
+  bool profiling = false;
+  hipEvent_t ev[2 * RPIM_N_PHASES] = {};
+  float phase_ms[RPIM_N_PHASES] = {};
+  bool phase_recorded[RPIM_N_PHASES] = {};
 };
 
 namespace rpim {
 
-// --- helpers (api.cpp) -----------------------------------------------------
+// phase timing helpers (api.hip)
+void phase_begin(rpim_plan* p, int phase, hipStream_t s);
+void phase_end(rpim_plan* p, int phase, hipStream_t s);
+
+// --- helpers (api.hip) -----------------------------------------------------
 rpim_status hip_ok(hipError_t e);
+// (Re)allocate *p to hold at least `count` elements; *cap tracks its capacity.
+rpim_status ensure_alloc(void** p, int64_t* cap, int64_t count, size_t elem);
+template <class T>
+inline rpim_status ensure(T** p, int64_t* cap, int64_t count) {
+  return ensure_alloc((void**)p, cap, count, sizeof(T));
+}
 #define RPIM_HIP(x)                                 \
   do {                                              \
     hipError_t e_ = (x);                            \

@@ -1,0 +1,56 @@
+"""C ABI surface checks that need no GPU: the library loads and exports every
+function that include/rpim.h declares; the oracle library loads too."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rpim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpim_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for required in ("rpim_build_pattern", "rpim_assemble", "rpim_assemble_backward", "rpim_apply_penalty_bc"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1802_04256_amd as rp
+    if not os.path.exists(rp.library_path()):
+        pytest.fail("librpim.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(rp.library_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    import paper_1802_04256_amd as rp
+    lib = rp.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        s = lib.rpim_status_string(code)
+        assert s and s != b"unknown status"
+
+
+def test_plan_create_rejects_bad_arguments():
+    import paper_1802_04256_amd as rp
+    lib = rp.lib()
+    # NULL problem / NULL out pointer are rejected before any device call
+    assert lib.rpim_plan_create(None, None) == -1
+    assert lib.rpim_plan_info(None, None) == -1
+    assert lib.rpim_get_status(None, None, None) == -1
+    assert lib.rpim_assemble(None, None, None, ctypes.c_double(0.3), 0, 0, None, None) == -1
+    assert lib.rpim_apply_penalty_bc(None, None, None, 0, 0, None, None, 0, ctypes.c_double(1.0), None, None,
+                                     None) == -1
+
+
+def test_package_has_no_cpu_fallback():
+    import paper_1802_04256_amd as rp
+    src = open(os.path.join(os.path.dirname(rp.__file__), "__init__.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
