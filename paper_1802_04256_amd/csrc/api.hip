@@ -162,7 +162,8 @@ void rpim_plan_destroy(rpim_plan* p) {
   (void)hipDeviceSynchronize();
   dfree(p->node_xyz0); dfree(p->gp_xyz); dfree(p->gp_wdet); dfree(p->gp_cell); dfree(p->d_gp_off); dfree(p->d_node_off);
   dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
-  dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
+  dfree(p->blk_col); dfree(p->blk_row); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
+  dfree(p->gp_order); dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
   dfree(p->lu_off); dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->msym); dfree(p->pbar); dfree(p->dEs); dfree(p->dEg); dfree(p->dXs);
   dfree(p->cell_ptr); dfree(p->cell_gp);
   dfree(p->status);
@@ -197,7 +198,7 @@ rpim_status rpim_rebuild_pattern(rpim_plan* p, const double* node_xyz, int64_t* 
   RPIM_HIP(hipStreamSynchronize(s));
   dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
   dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->lu_off);
-  dfree(p->cell_ptr); dfree(p->cell_gp);
+  dfree(p->cell_ptr); dfree(p->cell_gp); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
   p->built = false;
   p->have_factors = false;
   p->buckets.clear();

@@ -13,6 +13,7 @@
 //         dot = fma(pI2,pJ2, fma(pI1,pJ1, pI0 pJ0)).
 //   K   : +0 + e_g1 + e_g2 + ... over contributing points in ascending g.
 #include <cfloat>
+#include <cstdlib>
 
 #include "dd_pow.h"
 #include "rpim_internal.h"
@@ -84,7 +85,8 @@ __device__ __forceinline__ void argmax_pair(double v, int r, double* sv, int* sr
 // LDS: A[N][ld] (augmented with 3 right-hand sides), S[n], pivots[N].
 __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int64_t order_begin,
                                                     const int64_t* gp_ptr, const int32_t* gp_nbr,
-                                                    const int64_t* blk_ptr, const int32_t* blk_col, const double* R,
+                                                    const int64_t* blk_ptr, const int32_t* row_lo,
+                                                    const int64_t* rbm_off, const uint2* rbm, const double* R,
                                                     const double* X, const double* gp_xyz, double C2, double q,
                                                     int ld, double* dphi, int keep, const int64_t* lu_off,
                                                     double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
@@ -109,9 +111,7 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
   for (int idx = tid; idx < n * n; idx += kThreads) {
     const int a = idx / n, b = idx - a * n;
     if (b < a) continue;
-    const int32_t I = S[a];
-    const int64_t pos = find_sorted(blk_col, blk_ptr[I], blk_ptr[I + 1], S[b]);
-    const double v = R[pos];
+    const double v = R[block_pos(blk_ptr, row_lo, rbm_off, rbm, S[a], S[b])];
     A[a * ld + b] = v;
     A[b * ld + a] = v;
   }
@@ -213,7 +213,8 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 // ---- row gather: one workgroup per node row I --------------------------------
 // acc[pos][9] over the row's column blocks; contributions arrive in ascending g.
 template <bool kMixed>
-__global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
+__global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* row_lo,
+                                                        const int64_t* rbm_off, const uint2* rbm,
                                                         const int64_t* inv_ptr, const uint64_t* inv_key,
                                                         const int64_t* gp_ptr, const int32_t* gp_nbr,
                                                         const double* dphi, const double* wdet,
@@ -223,10 +224,13 @@ __global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, 
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* acc = smem;                       // [L][9] FP64, or [L][9] float2 (sum, compensation)
-  int32_t* cols = (int32_t*)(acc + 9 * L);  // [L]
+  double* acc = smem;                     // [L][9] FP64, or [L][9] float2 (sum, compensation)
+  uint2* bm = (uint2*)(acc + 9 * L);      // row I's rank bitmap
   const int tid = threadIdx.x;
-  for (int i = tid; i < L; i += kThreads) cols[i] = blk_col[rb + i];
+  const int lo_I = row_lo[I];
+  const int64_t wb = rbm_off[I];
+  const int nw = (int)(rbm_off[I + 1] - wb);
+  for (int i = tid; i < nw; i += kThreads) bm[i] = rbm[wb + i];
   for (int i = tid; i < 9 * L; i += kThreads) acc[i] = 0.0;
   __syncthreads();
   for (int64_t e = inv_ptr[I]; e < inv_ptr[I + 1]; ++e) {
@@ -242,11 +246,9 @@ __global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, 
       const int b = item / 3, al = item - 3 * b;
       const int32_t J = gp_nbr[b0 + b];
       const double pJ0 = dphi[3 * (b0 + b)], pJ1 = dphi[3 * (b0 + b) + 1], pJ2 = dphi[3 * (b0 + b) + 2];
-      int lo = 0, hi = L;
-      while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (cols[m] < J) lo = m + 1; else hi = m;
-      }
+      const int r = J - lo_I;
+      const uint2 wv = bm[r >> 5];
+      const int lo = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
       const double pI[3] = {pI0, pI1, pI2}, pJ[3] = {pJ0, pJ1, pJ2};
       if (!kMixed) {
         const double dot = __builtin_fma(pI2, pJ2, __builtin_fma(pI1, pJ1, pI0 * pJ0));
@@ -304,7 +306,14 @@ rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s) {
 rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s) {
   const double ac = p->alpha_c * p->d_c;
   const double C2 = ac * ac;
+  const char* sel = getenv("RPIM_SHAPE_KERNEL");
+  const bool use_reg = !(sel && sel[0] == 'l');  // "lds" selects the shared-memory kernel for every bucket
   for (const Bucket& b : p->buckets) {
+    if (use_reg && b.nmax <= shape_reg_max()) {
+      rpim_status st = launch_shape_reg(p, b, X, C2, keep, s);
+      if (st != RPIM_OK) return st;
+      continue;
+    }
     const int N = b.nmax;
     const int ld = ((N + 3) | 1);  // odd row stride in doubles
     const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
@@ -312,7 +321,8 @@ rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s)
     RPIM_HIP(hipFuncSetAttribute((const void*)k_shape, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
                        b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
+                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                       (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
                        p->dphi, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
     RPIM_HIP(hipGetLastError());
   }
@@ -325,20 +335,22 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   const double lam = nu / (onep * onem);
   const double mu = 1.0 / (2.0 * onep);
   const int L = (int)p->max_row_blocks;
-  const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(int32_t) * (size_t)L;
+  const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds > 160 * 1024) return RPIM_E_RANGE;
   if (precision == RPIM_FP64) {
     RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
     hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col, (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
+                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                       (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                        (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
   } else {
     RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
     hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col, (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
+                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                       (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                        (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
   }

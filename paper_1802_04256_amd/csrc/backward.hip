@@ -37,13 +37,14 @@ __device__ __forceinline__ int64_t find_sorted(const int32_t* v, int64_t b, int6
 
 // M = Kbar + Kbar^T, stored on the scalar CSR layout of K.
 __global__ void k_symmetrize(int64_t nblk, const int64_t* blk_ptr, const int32_t* blk_row, const int32_t* blk_col,
-                             const double* dK, double* M) {
+                             const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* dK,
+                             double* M) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nblk) return;
   const int32_t I = blk_row[e], J = blk_col[e];
   const int64_t bI = blk_ptr[I], LI = blk_ptr[I + 1] - bI, pI = e - bI;
   const int64_t bJ = blk_ptr[J], LJ = blk_ptr[J + 1] - bJ;
-  const int64_t pJ = find_sorted(blk_col, bJ, bJ + LJ, I) - bJ;
+  const int64_t pJ = block_pos(blk_ptr, row_lo, rbm_off, rbm, J, I) - bJ;
   for (int al = 0; al < 3; ++al)
     for (int be = 0; be < 3; ++be) {
       const int64_t o = 9 * bI + 3 * al * LI + 3 * pI + be;
@@ -69,7 +70,8 @@ __device__ __forceinline__ void block_sum4(double v[4], double (*sh)[kT / 64]) {
 }
 
 // Row gather: Phibar and dE share for each slot (g, a_I), I = blockIdx.x.
-__global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const int32_t* blk_col,
+__global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const int32_t* row_lo,
+                                                 const int64_t* rbm_off, const uint2* rbm,
                                                  const int64_t* inv_ptr, const uint64_t* inv_key,
                                                  const int64_t* gp_ptr, const int32_t* gp_nbr, const double* dphi,
                                                  const double* wdet, const int32_t* gp_cell, const double* E,
@@ -79,10 +81,13 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* Mrow = smem;                        // [L][9]  M_IJ blocks of row I
-  int32_t* cols = (int32_t*)(Mrow + 9 * L);   // [L]
+  double* Mrow = smem;                  // [L][9]  M_IJ blocks of row I
+  uint2* bm = (uint2*)(Mrow + 9 * L);   // row I's rank bitmap
   const int tid = threadIdx.x;
-  for (int i = tid; i < L; i += kT) cols[i] = blk_col[rb + i];
+  const int lo_I = row_lo[I];
+  const int64_t wb = rbm_off[I];
+  const int nw = (int)(rbm_off[I + 1] - wb);
+  for (int i = tid; i < nw; i += kT) bm[i] = rbm[wb + i];
   for (int idx = tid; idx < 9 * L; idx += kT) {
     const int pos = idx / 9, r = idx - 9 * pos, al = r / 3, be = r - 3 * al;
     Mrow[idx] = M[9 * rb + 3 * (int64_t)al * L + 3 * pos + be];
@@ -101,11 +106,9 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = tid; b < n; b += kT) {
       const int32_t J = gp_nbr[b0 + b];
-      int lo = 0, hi = L;
-      while (lo < hi) {
-        const int m = (lo + hi) >> 1;
-        if (cols[m] < J) lo = m + 1; else hi = m;
-      }
+      const int r = J - lo_I;
+      const uint2 wv = bm[r >> 5];
+      const int lo = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
       const double* Mb = Mrow + 9 * lo;
       const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
       const double tr = Mb[0] + Mb[4] + Mb[8];
@@ -138,7 +141,8 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
 // LDS: lambda[3][N], gamma[3][N], S[n].
 __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr,
                                                const int32_t* gp_nbr, const int64_t* blk_ptr,
-                                               const int32_t* blk_col, const double* R, const double* X,
+                                               const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm,
+                                               const double* R, const double* X,
                                                const double* gp_xyz, double C2, double q, const int64_t* lu_off,
                                                const double* lu, const int32_t* piv, const double* gam,
                                                const double* pbar, double* dXs) {
@@ -192,8 +196,6 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   // chain rule per support node a
   for (int a = tid; a < n; a += kT) {
     const double* xa = X + 3 * (int64_t)S[a];
-    const int32_t I = S[a];
-    const int64_t rb = blk_ptr[I], re = blk_ptr[I + 1];
     double acc[3] = {0.0, 0.0, 0.0};
     const double la[3] = {lamv[a], lamv[N + a], lamv[2 * N + a]};
     const double ga[3] = {gm[a], gm[N + a], gm[2 * N + a]};
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
                             lamv[N + b] * ga[1] + lamv[2 * N + b] * ga[2]);
       const double dx = xa[0] - xb[0], dy = xa[1] - xb[1], dz = xa[2] - xb[2];
       const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
-      const double Rab = R[find_sorted(blk_col, rb, re, S[b])];
+      const double Rab = R[block_pos(blk_ptr, row_lo, rbm_off, rbm, S[a], S[b])];
       const double f = gsum * (q * Rab / t) * 2.0;
       acc[0] += f * dx;
       acc[1] += f * dy;
@@ -286,14 +288,15 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   phase_begin(p, RPIM_PHASE_BWD_ROWS, s);
   if (p->nblk > 0)
     hipLaunchKernelGGL(k_symmetrize, dim3(nblocks(p->nblk, 256)), dim3(256), 0, s, p->nblk,
-                       (const int64_t*)p->blk_ptr, (const int32_t*)p->blk_row, (const int32_t*)p->blk_col, dK,
-                       p->msym);
+                       (const int64_t*)p->blk_ptr, (const int32_t*)p->blk_row, (const int32_t*)p->blk_col,
+                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm, dK, p->msym);
   const int L = (int)p->max_row_blocks;
-  const size_t lds_rows = sizeof(double) * 9 * (size_t)L + sizeof(int32_t) * (size_t)L;
+  const size_t lds_rows = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds_rows > 160 * 1024) return RPIM_E_RANGE;
   RPIM_HIP(hipFuncSetAttribute((const void*)k_bwd_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_rows));
   hipLaunchKernelGGL(k_bwd_rows, dim3((unsigned)p->N), dim3(kT), lds_rows, s, (const int64_t*)p->blk_ptr,
-                     (const int32_t*)p->blk_col, (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
+                     (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                     (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                      (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                      (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, (const double*)p->msym,
                      p->pbar, p->dEs);
@@ -305,7 +308,8 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
     const size_t lds = sizeof(double) * 6 * (size_t)N + sizeof(int) * (size_t)N;
     hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(kT), lds, s, (const int32_t*)p->gp_order, b.begin,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q,
+                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                       (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q,
                        (const int64_t*)p->lu_off, (const double*)p->lu, (const int32_t*)p->piv,
                        (const double*)p->gam, (const double*)p->pbar, p->dXs);
     RPIM_HIP(hipGetLastError());

@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256) k_blocks(const int64_t* inv_ptr, const ui
                                                 const int64_t* gp_ptr, const int32_t* gp_nbr,
                                                 const int32_t* win_lo, const int32_t* win_len, int words,
                                                 int32_t* blk_cnt, const int64_t* blk_ptr, int32_t* blk_col,
-                                                int32_t* blk_row) {
+                                                int32_t* blk_row, const int64_t* rbm_off, uint2* rbm) {
   extern __shared__ unsigned bm[];
   const int64_t I = blockIdx.x;
   const int lo = win_lo[I];
@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(256) k_blocks(const int64_t* inv_ptr, const ui
   int k = 0;
   for (int i = w0; i < w1; ++i) {
     unsigned v = bm[i];
+    rbm[rbm_off[I] + i] = make_uint2(v, (unsigned)(pos + k));
     while (v) {
       const int bit = __ffs(v) - 1;
       v &= v - 1;
@@ -444,10 +445,26 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   if (max_win > kMaxWindow) return RPIM_E_RANGE;
   const int words = (int)((max_win + 31) / 32);
   blk_cnt = counts;  // reuse (size >= N)
+  // per-row rank bitmaps: word offsets from the window lengths
+  {
+    std::vector<int64_t> off(N + 1, 0);
+    int32_t mw = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      const int32_t nw = (cnt_h[i] + 31) / 32;
+      off[i + 1] = off[i] + nw;
+      mw = std::max(mw, nw);
+    }
+    p->rbm_words = off[N];
+    p->max_row_words = mw;
+    RPIM_HIP(hipMalloc((void**)&p->rbm_off, sizeof(int64_t) * (N + 1)));
+    RPIM_HIP(hipMalloc((void**)&p->rbm, sizeof(uint2) * std::max<int64_t>(off[N], 1)));
+    RPIM_HIP(hipMemcpyAsync(p->rbm_off, off.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice, s));
+  }
   hipLaunchKernelGGL(k_blocks<false>, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr,
                      (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, words, blk_cnt,
-                     (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr);
+                     (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
+                     (uint2*)nullptr);
   RPIM_HIP(hipGetLastError());
   RPIM_HIP(hipMalloc((void**)&p->blk_ptr, sizeof(int64_t) * (N + 1)));
   st = exclusive_scan(blk_cnt, N, p->blk_ptr, s);
@@ -465,7 +482,8 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   hipLaunchKernelGGL(k_blocks<true>, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr,
                      (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, words,
-                     (int32_t*)nullptr, (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row);
+                     (int32_t*)nullptr, (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row,
+                     (const int64_t*)p->rbm_off, p->rbm);
   RPIM_HIP(hipGetLastError());
 
   // buckets by padded moment-matrix size, and LU offsets (host, from gp_ptr)
@@ -531,7 +549,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipFree(counts));
   RPIM_HIP(hipFree(inv_cnt));
   RPIM_HIP(hipFree(cursor));
-  RPIM_HIP(hipFree(win_lo));
+  p->row_lo = win_lo;
   RPIM_HIP(hipFree(win_len));
   p->built = true;
   return RPIM_OK;

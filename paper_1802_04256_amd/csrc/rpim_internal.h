@@ -34,6 +34,14 @@ struct BinGrid {
 };
 
 // Gauss points with the same padded moment-matrix size share a bucket.
+// Position of column J in node-block row I through the row's rank bitmap.
+__device__ __forceinline__ int64_t block_pos(const int64_t* blk_ptr, const int32_t* row_lo, const int64_t* rbm_off,
+                                             const uint2* rbm, int32_t I, int32_t J) {
+  const int r = J - row_lo[I];
+  const uint2 w = rbm[rbm_off[I] + (r >> 5)];
+  return blk_ptr[I] + (int64_t)w.y + __popc(w.x & ((1u << (r & 31)) - 1u));
+}
+
 struct Bucket {
   int nmax;        // largest N = n + 4 in the bucket
   int64_t begin;   // range in gp_order
@@ -69,6 +77,14 @@ struct rpim_plan {
   int64_t* blk_ptr = nullptr;    // [N+1]
   int32_t* blk_col = nullptr;    // [nblk]
   int32_t* blk_row = nullptr;    // [nblk]
+  // rank structure of each node-block row over its node-id window:
+  // word i of row I covers ids lo_I + 32 i ... + 31; .x = bits, .y = set bits in words < i.
+  // position of column J in row I = blk_ptr[I] + y + popc(x & ((1 << b) - 1)).
+  int32_t* row_lo = nullptr;     // [N]   first id of the window (= smallest column)
+  int64_t* rbm_off = nullptr;    // [N+1] word offsets
+  uint2* rbm = nullptr;          // [rbm_off[N]]
+  int64_t rbm_words = 0;
+  int32_t max_row_words = 0;
   int64_t max_row_blocks = 0;    // longest node-block row
   int64_t max_inverse = 0;       // longest inverse list
   std::vector<rpim::Bucket> buckets;
@@ -142,6 +158,8 @@ rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s);
 rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s);
 rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K,
                              hipStream_t s);
+int shape_reg_max();
+rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, hipStream_t s);
 rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s);
 
 // --- backward.hip ------------------------------------------------------------
