@@ -120,7 +120,7 @@ rpim_status rpim_plan_create(const rpim_problem* problem, rpim_plan** plan);
  *   row_ptr int64[3N + 1], col_idx int32[nnz] (device).
  * Typical use: call once with NULLs to learn nnz, allocate, call again.
  * RPIM_E_SUPPORT if some |S_g| < 5 (rpim_get_status gives the first such g);
- * RPIM_E_RANGE if a support exceeds 256 nodes, a node lies in more than 8192
+ * RPIM_E_RANGE if a support exceeds 132 nodes, a node lies in more than 8192
  * supports, or the node ids in a node's neighbourhood span more than 2^18. */
 rpim_status rpim_build_pattern(rpim_plan* plan, int64_t* row_ptr, int32_t* col_idx, int64_t* nnz,
                                void* stream);

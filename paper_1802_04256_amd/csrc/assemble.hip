@@ -101,8 +101,9 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
   const int N = n + 4, W = N + 3;
   double* A = smem;
   int* S = (int*)(A + (size_t)N * ld);
-  int* pv = S + n;
+  int* pv = S + n;  // original row now at each position
   for (int i = tid; i < n; i += kThreads) S[i] = gp_nbr[b0 + i];
+  for (int i = tid; i < N; i += kThreads) pv[i] = i;
   for (int i = tid; i < N * ld; i += kThreads) A[i] = 0.0;
   if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
   __syncthreads();
@@ -159,7 +160,11 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
     int p;
     argmax_pair(v, r, red_v, red_r, &best, &p);
     if (!(best > tiny)) { singular = true; break; }
-    if (tid == 0) pv[k] = p;
+    if (tid == 0 && p != k) {
+      const int t = pv[k];
+      pv[k] = pv[p];
+      pv[p] = t;
+    }
     if (p != k)
       for (int c = tid; c < W; c += kThreads) {
         const double t = A[k * ld + c];
@@ -196,10 +201,12 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
     dphi[3 * (b0 + a) + k] = A[a * ld + N + k];
   }
   if (keep) {
-    double* L = lu + lu_off[g];  // column-major: the adjoint solves walk columns
+    double* L = lu + lu_off[g];  // multipliers by (step, original row), then U rows by position
+    double* U = L + (int64_t)N * N;
     for (int idx = tid; idx < N * N; idx += kThreads) {
-      const int c = idx / N, r = idx - c * N;
-      L[idx] = A[r * ld + c];
+      const int r = idx / N, c = idx - r * N;  // position r, column c
+      if (c < r) L[(int64_t)c * N + pv[r]] = A[r * ld + c];
+      else U[(int64_t)c * N + r] = A[r * ld + c];
     }
     const int64_t o = b0 + 4 * g;
     for (int i = tid; i < N; i += kThreads) piv_out[o + i] = pv[i];
@@ -211,62 +218,120 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 }
 
 // ---- row gather: one workgroup per node row I --------------------------------
-// acc[pos][9] over the row's column blocks; contributions arrive in ascending g.
+// acc[pos][9] over the row's column blocks.  Wave w owns the accumulators of
+// displacement component alpha = w (three waves), so the waves never touch the
+// same slot; each wave walks the row's Gauss points in ascending g and, since
+// a wave's LDS accesses execute in program order, every slot receives its
+// contributions in ascending g without any barrier.
+constexpr int kGatherThreads = 192;
+
 template <bool kMixed>
-__global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* row_lo,
-                                                        const int64_t* rbm_off, const uint2* rbm,
-                                                        const int64_t* inv_ptr, const uint64_t* inv_key,
-                                                        const int64_t* gp_ptr, const int32_t* gp_nbr,
-                                                        const double* dphi, const double* wdet,
-                                                        const int32_t* gp_cell, const double* E, double lam,
-                                                        double mu, void* Kout) {
+__global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* row_lo,
+                                                              const int64_t* rbm_off, const uint2* rbm,
+                                                              const int64_t* inv_ptr, const uint64_t* inv_key,
+                                                              const int64_t* gp_ptr, const int32_t* gp_nbr,
+                                                              const double* dphi, const double* wdet,
+                                                              const int32_t* gp_cell, const double* E, double lam,
+                                                              double mu, void* Kout) {
   extern __shared__ double smem[];
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* acc = smem;                     // [L][9] FP64, or [L][9] float2 (sum, compensation)
-  uint2* bm = (uint2*)(acc + 9 * L);      // row I's rank bitmap
+  double* acc = smem;                 // [L][9] FP64, or [L][9] float2 (sum, compensation)
+  uint2* bm = (uint2*)(acc + 9 * L);  // row I's rank bitmap
   const int tid = threadIdx.x;
+  const int al = tid >> 6, lane = tid & 63;
   const int lo_I = row_lo[I];
   const int64_t wb = rbm_off[I];
   const int nw = (int)(rbm_off[I + 1] - wb);
-  for (int i = tid; i < nw; i += kThreads) bm[i] = rbm[wb + i];
-  for (int i = tid; i < 9 * L; i += kThreads) acc[i] = 0.0;
+  for (int i = tid; i < nw; i += kGatherThreads) bm[i] = rbm[wb + i];
+  for (int i = tid; i < 9 * L; i += kGatherThreads) acc[i] = 0.0;
   __syncthreads();
-  for (int64_t e = inv_ptr[I]; e < inv_ptr[I + 1]; ++e) {
+  // Two-stage software pipeline over the row's Gauss points: point metadata
+  // (scalar) is fetched two points ahead, the per-lane support entries one
+  // point ahead, so the dependent global loads overlap the accumulation.
+  struct Meta {
+    int64_t b0;
+    int n, aI;
+    double lc, mc;
+  };
+  const int64_t e_beg = inv_ptr[I], e_end = inv_ptr[I + 1];
+  auto meta = [&](int64_t e) {
+    Meta m;
     const uint64_t key = inv_key[e];
     const int64_t g = (int64_t)(key >> 8);
-    const int aI = (int)(key & 255);
-    const int64_t b0 = gp_ptr[g];
-    const int n = (int)(gp_ptr[g + 1] - b0);
+    m.aI = (int)(key & 255);
+    m.b0 = gp_ptr[g];
+    m.n = (int)(gp_ptr[g + 1] - m.b0);
     const double c = wdet[g] * E[gp_cell[g]];
-    const double lc = c * lam, mc = c * mu;
-    const double pI0 = dphi[3 * (b0 + aI)], pI1 = dphi[3 * (b0 + aI) + 1], pI2 = dphi[3 * (b0 + aI) + 2];
-    for (int item = tid; item < 3 * n; item += kThreads) {
-      const int b = item / 3, al = item - 3 * b;
-      const int32_t J = gp_nbr[b0 + b];
-      const double pJ0 = dphi[3 * (b0 + b)], pJ1 = dphi[3 * (b0 + b) + 1], pJ2 = dphi[3 * (b0 + b) + 2];
+    m.lc = c * lam;
+    m.mc = c * mu;
+    return m;
+  };
+  struct Lanes {
+    int32_t J[2];
+    double pJ[2][3];
+    double pI[3];
+  };
+  auto lanes = [&](const Meta& m) {
+    Lanes l;
+    for (int k = 0; k < 3; ++k) l.pI[k] = dphi[3 * (m.b0 + m.aI) + k];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int b = lane + 64 * s2;
+      l.J[s2] = -1;
+      if (b < m.n) {
+        l.J[s2] = gp_nbr[m.b0 + b];
+        for (int k = 0; k < 3; ++k) l.pJ[s2][k] = dphi[3 * (m.b0 + b) + k];
+      } else {
+        for (int k = 0; k < 3; ++k) l.pJ[s2][k] = 0.0;
+      }
+    }
+    return l;
+  };
+  Meta m_cur = {}, m_nxt = {};
+  Lanes l_cur = {};
+  if (e_beg < e_end) {
+    m_cur = meta(e_beg);
+    l_cur = lanes(m_cur);
+  }
+  if (e_beg + 1 < e_end) m_nxt = meta(e_beg + 1);
+  for (int64_t e = e_beg; e < e_end; ++e) {
+    Meta m_nn = {};
+    if (e + 2 < e_end) m_nn = meta(e + 2);
+    Lanes l_nxt = {};
+    if (e + 1 < e_end) l_nxt = lanes(m_nxt);
+    const double lc = m_cur.lc, mc = m_cur.mc;
+    const double pI0 = l_cur.pI[0], pI1 = l_cur.pI[1], pI2 = l_cur.pI[2];
+    // this wave's component alpha of phi_I (no dynamic register indexing)
+    const double pIa = al == 0 ? pI0 : (al == 1 ? pI1 : pI2);
+    auto accum = [&](int32_t J, double pJ0, double pJ1, double pJ2) {
       const int r = J - lo_I;
       const uint2 wv = bm[r >> 5];
-      const int lo = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
-      const double pI[3] = {pI0, pI1, pI2}, pJ[3] = {pJ0, pJ1, pJ2};
+      const int pos = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
+      const double pJa = al == 0 ? pJ0 : (al == 1 ? pJ1 : pJ2);
+      const double pJb[3] = {pJ0, pJ1, pJ2};
+      const double pIb[3] = {pI0, pI1, pI2};
       if (!kMixed) {
         const double dot = __builtin_fma(pI2, pJ2, __builtin_fma(pI1, pJ1, pI0 * pJ0));
-        double* a = acc + 9 * lo + 3 * al;
+        double* a = acc + 9 * pos + 3 * al;
+#pragma unroll
         for (int be = 0; be < 3; ++be) {
-          const double m1 = pI[al] * pJ[be];
-          double m2 = pI[be] * pJ[al];
+          const double m1 = pIa * pJb[be];
+          double m2 = pIb[be] * pJa;
           if (al == be) m2 = m2 + dot;
           a[be] = a[be] + __builtin_fma(lc, m1, mc * m2);
         }
       } else {
+        const float fIa = (float)pIa, fJa = (float)pJa;
         const float fI[3] = {(float)pI0, (float)pI1, (float)pI2}, fJ[3] = {(float)pJ0, (float)pJ1, (float)pJ2};
         const float flc = (float)lc, fmc = (float)mc;
         const float dot = __builtin_fmaf(fI[2], fJ[2], __builtin_fmaf(fI[1], fJ[1], fI[0] * fJ[0]));
-        float2* a = reinterpret_cast<float2*>(acc) + 9 * lo + 3 * al;
+        float2* a = reinterpret_cast<float2*>(acc) + 9 * pos + 3 * al;
+#pragma unroll
         for (int be = 0; be < 3; ++be) {
-          const float m1 = fI[al] * fJ[be];
-          float m2 = fI[be] * fJ[al];
+          const float m1 = fIa * fJ[be];
+          float m2 = fI[be] * fJa;
           if (al == be) m2 = m2 + dot;
           const float ev = __builtin_fmaf(flc, m1, fmc * m2);
           float2 sc = a[be];
@@ -277,13 +342,23 @@ __global__ void __launch_bounds__(kThreads) k_rowgather(const int64_t* blk_ptr, 
           a[be] = sc;
         }
       }
+    };
+    if (l_cur.J[0] >= 0) accum(l_cur.J[0], l_cur.pJ[0][0], l_cur.pJ[0][1], l_cur.pJ[0][2]);
+    if (l_cur.J[1] >= 0) accum(l_cur.J[1], l_cur.pJ[1][0], l_cur.pJ[1][1], l_cur.pJ[1][2]);
+    // supports beyond 128 nodes (rare) take a plain loop after the two prefetched slots
+    for (int b = 128 + lane; b < m_cur.n; b += 64) {
+      const int64_t eb = m_cur.b0 + b;
+      accum(gp_nbr[eb], dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]);
     }
-    __syncthreads();
+    m_cur = m_nxt;
+    l_cur = l_nxt;
+    m_nxt = m_nn;
   }
+  __syncthreads();
   const int64_t base = 9 * rb;
-  for (int idx = tid; idx < 9 * L; idx += kThreads) {
-    const int pos = idx / 9, r = idx - 9 * pos, al = r / 3, be = r - 3 * al;
-    const int64_t o = base + 3 * (int64_t)al * L + 3 * pos + be;
+  for (int idx = tid; idx < 9 * L; idx += kGatherThreads) {
+    const int pos = idx / 9, r = idx - 9 * pos, a = r / 3, be = r - 3 * a;
+    const int64_t o = base + 3 * (int64_t)a * L + 3 * pos + be;
     if (!kMixed) ((double*)Kout)[o] = acc[idx];
     else ((float*)Kout)[o] = reinterpret_cast<float2*>(acc)[idx].x;
   }
@@ -340,7 +415,7 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   if (precision == RPIM_FP64) {
     RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
-    hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
+    hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
@@ -348,7 +423,7 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   } else {
     RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds));
-    hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kThreads), lds, s, (const int64_t*)p->blk_ptr,
+    hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,

@@ -53,23 +53,9 @@ __global__ void k_symmetrize(int64_t nblk, const int64_t* blk_ptr, const int32_t
     }
 }
 
-// Sum of 4 values over the block; result valid in every thread.
-__device__ __forceinline__ void block_sum4(double v[4], double (*sh)[kT / 64]) {
-  for (int o = 32; o > 0; o >>= 1)
-    for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0)
-    for (int i = 0; i < 4; ++i) sh[i][w] = v[i];
-  __syncthreads();
-  for (int i = 0; i < 4; ++i) {
-    double s = 0.0;
-    for (int k = 0; k < kT / 64; ++k) s += sh[i][k];
-    v[i] = s;
-  }
-  __syncthreads();
-}
-
 // Row gather: Phibar and dE share for each slot (g, a_I), I = blockIdx.x.
+// Slots are independent, so each wave takes its own Gauss points (lanes over
+// the support) and reduces within the wave: no barriers after the row load.
 __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const int32_t* row_lo,
                                                  const int64_t* rbm_off, const uint2* rbm,
                                                  const int64_t* inv_ptr, const uint64_t* inv_key,
@@ -77,13 +63,12 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
                                                  const double* wdet, const int32_t* gp_cell, const double* E,
                                                  double lam, double mu, const double* M, double* pbar, double* dEs) {
   extern __shared__ double smem[];
-  __shared__ double red[4][kT / 64];
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
   double* Mrow = smem;                  // [L][9]  M_IJ blocks of row I
   uint2* bm = (uint2*)(Mrow + 9 * L);   // row I's rank bitmap
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int lo_I = row_lo[I];
   const int64_t wb = rbm_off[I];
   const int nw = (int)(rbm_off[I + 1] - wb);
@@ -93,7 +78,7 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
     Mrow[idx] = M[9 * rb + 3 * (int64_t)al * L + 3 * pos + be];
   }
   __syncthreads();
-  for (int64_t e = inv_ptr[I]; e < inv_ptr[I + 1]; ++e) {
+  for (int64_t e = inv_ptr[I] + wv; e < inv_ptr[I + 1]; e += kT / 64) {
     const uint64_t key = inv_key[e];
     const int64_t g = (int64_t)(key >> 8);
     const int aI = (int)(key & 255);
@@ -104,12 +89,12 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
     const double lc = c * lam, mc = c * mu;
     const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = tid; b < n; b += kT) {
+    for (int b = lane; b < n; b += 64) {
       const int32_t J = gp_nbr[b0 + b];
       const int r = J - lo_I;
-      const uint2 wv = bm[r >> 5];
-      const int lo = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
-      const double* Mb = Mrow + 9 * lo;
+      const uint2 bw = bm[r >> 5];
+      const int pos = (int)bw.y + __popc(bw.x & ((1u << (r & 31)) - 1u));
+      const double* Mb = Mrow + 9 * pos;
       const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
       const double tr = Mb[0] + Mb[4] + Mb[8];
       for (int ga = 0; ga < 3; ++ga) {
@@ -126,8 +111,11 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
         }
       v[3] += 0.5 * w * kk;
     }
-    block_sum4(v, red);
-    if (tid == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 64);
+    if (lane == 0) {
       const int64_t slot = b0 + aI;
       pbar[3 * slot] = v[0];
       pbar[3 * slot + 1] = v[1];
@@ -138,7 +126,11 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
 }
 
 // Per Gauss point: adjoint solves with the kept LU, then the chain rule.
-// LDS: lambda[3][N], gamma[3][N], S[n].
+// Thread r owns original row r for the forward substitution and position r
+// for the back substitution (right-hand sides in registers); each step's
+// factor entry is loaded before the step's barrier.  The chain rule runs over
+// (a, b) pairs with four threads per support node a and a fixed-order
+// shuffle reduction of their partial sums.
 __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr,
                                                const int32_t* gp_nbr, const int64_t* blk_ptr,
                                                const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm,
@@ -153,84 +145,118 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   const int64_t b0 = gp_ptr[g];
   const int n = (int)(gp_ptr[g + 1] - b0);
   const int N = n + 4;
-  double* lamv = smem;          // [3][N]
-  double* gm = lamv + 3 * N;    // [3][N]
-  int* S = (int*)(gm + 3 * N);  // [n]
+  double* lamv = smem;            // [3][N] solution lambda_k (by unknown)
+  double* gm = lamv + 3 * N;      // [3][N] gamma_k
+  double* y = gm + 3 * N;         // [3][N] forward values by position
+  double* xs = y + 3 * N;         // [n][3] support coordinates
+  int* S = (int*)(xs + 3 * n);    // [n]
+  int* rowat = S + n;             // [N] original row at each position
+  int* posf = rowat + N;          // [N] final position of each original row
   const int64_t o = b0 + 4 * g;
-  const double* LU = lu + lu_off[g];  // column-major
-  for (int idx = tid; idx < 3 * N; idx += kT) {
-    const int k = idx / N, i = idx - k * N;
-    lamv[idx] = i < n ? pbar[3 * (b0 + i) + k] : 0.0;
-    gm[idx] = gam[3 * o + idx];
+  const double* Lm = lu + lu_off[g];      // multipliers [k][original row]
+  const double* U = Lm + (int64_t)N * N;  // U column-major by position
+  for (int idx = tid; idx < 3 * N; idx += kT) gm[idx] = gam[3 * o + idx];
+  for (int i = tid; i < n; i += kT) {
+    const int32_t sidx = gp_nbr[b0 + i];
+    S[i] = sidx;
+    for (int k = 0; k < 3; ++k) xs[3 * i + k] = X[3 * (int64_t)sidx + k];
   }
-  for (int i = tid; i < n; i += kT) S[i] = gp_nbr[b0 + i];
+  for (int i = tid; i < N; i += kT) rowat[i] = piv[o + i];
   if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
   __syncthreads();
-  // row swaps in factorisation order
-  if (tid < 3) {
-    double* b = lamv + tid * N;
-    for (int k = 0; k < N; ++k) {
-      const int p = piv[o + k];
-      if (p != k) { const double t = b[k]; b[k] = b[p]; b[p] = t; }
-    }
+  for (int i = tid; i < N; i += kT) posf[rowat[i]] = i;
+  // right-hand side [Phibar_k; 0] of my original row
+  const bool own = tid < N;
+  double b[3] = {0.0, 0.0, 0.0};
+  if (own && tid < n)
+    for (int k = 0; k < 3; ++k) b[k] = pbar[3 * (b0 + tid) + k];
+  __syncthreads();
+  const int my_posf = own ? posf[tid] : -1;
+  // forward substitution on original rows
+  double lnext = (own && N > 0) ? Lm[tid] : 0.0;
+  for (int k = 0; k < N; ++k) {
+    const double lk = lnext;
+    if (own && k + 1 < N) lnext = Lm[(int64_t)(k + 1) * N + tid];
+    if (own && my_posf == k)
+      for (int j = 0; j < 3; ++j) y[j * N + k] = b[j];
+    __syncthreads();
+    if (own && my_posf > k)
+      for (int j = 0; j < 3; ++j) b[j] = __builtin_fma(-lk, y[j * N + k], b[j]);
   }
   __syncthreads();
-  // forward substitution with unit lower L
-  for (int k = 0; k < N - 1; ++k) {
-    for (int idx = tid; idx < 3 * (N - k - 1); idx += kT) {
-      const int j = idx / (N - k - 1), r = k + 1 + idx % (N - k - 1);
-      lamv[j * N + r] = __builtin_fma(-LU[(int64_t)k * N + r], lamv[j * N + k], lamv[j * N + r]);
-    }
-    __syncthreads();
-  }
-  // back substitution with U
+  // back substitution by position: thread p holds y_p
+  double yp[3] = {0.0, 0.0, 0.0};
+  if (own)
+    for (int j = 0; j < 3; ++j) yp[j] = y[j * N + tid];
+  double unext = own ? U[(int64_t)(N - 1) * N + tid] : 0.0;
   for (int k = N - 1; k >= 0; --k) {
-    if (tid < 3) lamv[tid * N + k] = lamv[tid * N + k] / LU[(int64_t)k * N + k];
-    __syncthreads();
-    for (int idx = tid; idx < 3 * k; idx += kT) {
-      const int j = idx / k, r = idx - j * k;
-      lamv[j * N + r] = __builtin_fma(-LU[(int64_t)k * N + r], lamv[j * N + k], lamv[j * N + r]);
-    }
-    __syncthreads();
-  }
-  // chain rule per support node a
-  for (int a = tid; a < n; a += kT) {
-    const double* xa = X + 3 * (int64_t)S[a];
-    double acc[3] = {0.0, 0.0, 0.0};
-    const double la[3] = {lamv[a], lamv[N + a], lamv[2 * N + a]};
-    const double ga[3] = {gm[a], gm[N + a], gm[2 * N + a]};
-    for (int b = 0; b < n; ++b) {
-      if (b == a) continue;
-      const double* xb = X + 3 * (int64_t)S[b];
-      const double gsum = -(la[0] * gm[b] + la[1] * gm[N + b] + la[2] * gm[2 * N + b] + lamv[b] * ga[0] +
-                            lamv[N + b] * ga[1] + lamv[2 * N + b] * ga[2]);
-      const double dx = xa[0] - xb[0], dy = xa[1] - xb[1], dz = xa[2] - xb[2];
-      const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
-      const double Rab = R[block_pos(blk_ptr, row_lo, rbm_off, rbm, S[a], S[b])];
-      const double f = gsum * (q * Rab / t) * 2.0;
-      acc[0] += f * dx;
-      acc[1] += f * dy;
-      acc[2] += f * dz;
-    }
-    for (int k = 0; k < 3; ++k) {
-      const int i = n + 1 + k;
-      acc[k] -= la[0] * gm[i] + la[1] * gm[N + i] + la[2] * gm[2 * N + i] + lamv[i] * ga[0] + lamv[N + i] * ga[1] +
-                lamv[2 * N + i] * ga[2];
-    }
-    const double dgx[3] = {xg[0] - xa[0], xg[1] - xa[1], xg[2] - xa[2]};
-    const double t = __builtin_fma(-dgx[2], -dgx[2], __builtin_fma(-dgx[1], -dgx[1], dgx[0] * dgx[0])) + C2;
-    bool hard = false;
-    const double Rg = pow_cr(t, q, &hard);
-    const double tq1 = Rg / t, tq2 = Rg / (t * t);
-    for (int cc = 0; cc < 3; ++cc) {
-      double s = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        const double dr = -(4.0 * q * (q - 1.0) * tq2 * dgx[cc] * dgx[k] + (k == cc ? 2.0 * q * tq1 : 0.0));
-        s += la[k] * dr;
+    const double uk = unext;  // u_{tid,k}
+    if (own && k > 0) unext = U[(int64_t)(k - 1) * N + tid];
+    if (tid == k)
+      for (int j = 0; j < 3; ++j) {
+        yp[j] = yp[j] / uk;
+        lamv[j * N + k] = yp[j];
       }
-      acc[cc] += s;
+    __syncthreads();
+    if (tid < k)
+      for (int j = 0; j < 3; ++j) yp[j] = __builtin_fma(-uk, lamv[j * N + k], yp[j]);
+  }
+  __syncthreads();
+  // chain rule: four threads per support node a, partial sums over b = sub mod 4
+  for (int a0 = 0; a0 < n; a0 += kT / 4) {
+    const int a = a0 + tid / 4, sub = tid & 3;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (a < n) {
+      const double xa[3] = {xs[3 * a], xs[3 * a + 1], xs[3 * a + 2]};
+      const double la[3] = {lamv[a], lamv[N + a], lamv[2 * N + a]};
+      const double ga[3] = {gm[a], gm[N + a], gm[2 * N + a]};
+      const int32_t Ia = S[a];
+      const int lo_a = row_lo[Ia];
+      const int64_t wb_a = rbm_off[Ia], bp_a = blk_ptr[Ia];
+      for (int bb = sub; bb < n; bb += 4) {
+        if (bb == a) continue;
+        const double gsum = -(la[0] * gm[bb] + la[1] * gm[N + bb] + la[2] * gm[2 * N + bb] + lamv[bb] * ga[0] +
+                              lamv[N + bb] * ga[1] + lamv[2 * N + bb] * ga[2]);
+        const double dx = xa[0] - xs[3 * bb], dy = xa[1] - xs[3 * bb + 1], dz = xa[2] - xs[3 * bb + 2];
+        const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
+        const int r = S[bb] - lo_a;
+        const uint2 wv = rbm[wb_a + (r >> 5)];
+        const double Rab = R[bp_a + (int64_t)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u))];
+        const double f = gsum * (q * Rab / t) * 2.0;
+        acc[0] += f * dx;
+        acc[1] += f * dy;
+        acc[2] += f * dz;
+      }
     }
-    for (int k = 0; k < 3; ++k) dXs[3 * (b0 + a) + k] = acc[k];
+    // fixed-order reduction over the four threads of each node
+    for (int k = 0; k < 3; ++k) {
+      acc[k] += __shfl_xor(acc[k], 1, 64);
+      acc[k] += __shfl_xor(acc[k], 2, 64);
+    }
+    if (a < n && sub == 0) {
+      const double xa[3] = {xs[3 * a], xs[3 * a + 1], xs[3 * a + 2]};
+      const double la[3] = {lamv[a], lamv[N + a], lamv[2 * N + a]};
+      const double ga[3] = {gm[a], gm[N + a], gm[2 * N + a]};
+      for (int k = 0; k < 3; ++k) {
+        const int i = n + 1 + k;
+        acc[k] -= la[0] * gm[i] + la[1] * gm[N + i] + la[2] * gm[2 * N + i] + lamv[i] * ga[0] +
+                  lamv[N + i] * ga[1] + lamv[2 * N + i] * ga[2];
+      }
+      const double dgx[3] = {xg[0] - xa[0], xg[1] - xa[1], xg[2] - xa[2]};
+      const double t = __builtin_fma(-dgx[2], -dgx[2], __builtin_fma(-dgx[1], -dgx[1], dgx[0] * dgx[0])) + C2;
+      bool hard = false;
+      const double Rg = pow_cr(t, q, &hard);
+      const double tq1 = Rg / t, tq2 = Rg / (t * t);
+      for (int cc = 0; cc < 3; ++cc) {
+        double s2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double dr = -(4.0 * q * (q - 1.0) * tq2 * dgx[cc] * dgx[k] + (k == cc ? 2.0 * q * tq1 : 0.0));
+          s2 += la[k] * dr;
+        }
+        acc[cc] += s2;
+      }
+      for (int k = 0; k < 3; ++k) dXs[3 * (b0 + a) + k] = acc[k];
+    }
   }
 }
 
@@ -305,7 +331,7 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   phase_begin(p, RPIM_PHASE_BWD_GP, s);
   for (const Bucket& b : p->buckets) {
     const int N = b.nmax;
-    const size_t lds = sizeof(double) * 6 * (size_t)N + sizeof(int) * (size_t)N;
+    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int) * (size_t)(3 * N);
     hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(kT), lds, s, (const int32_t*)p->gp_order, b.begin,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,

@@ -498,7 +498,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     p->min_n = std::min(p->min_n, n);
     p->max_n = std::max(p->max_n, n);
     bcount[(n + 4 + kBucketStep - 1) / kBucketStep]++;
-    lu_off_h[g + 1] = lu_off_h[g] + (int64_t)(n + 4) * (n + 4);
+    lu_off_h[g + 1] = lu_off_h[g] + 2 * (int64_t)(n + 4) * (n + 4);  // multipliers + U rows
   }
   p->lu_doubles = lu_off_h[G];
   p->buckets.clear();

@@ -11,7 +11,7 @@
 namespace rpim {
 
 // Limits (documented in rpim.h).
-constexpr int kMaxSupport = 256;        // nodes per support
+constexpr int kMaxSupport = 132;        // nodes per support (N = n + 4 <= 136 fits the LDS solver)
 constexpr int kMaxInverse = 8192;       // supports containing one node
 constexpr int64_t kMaxWindow = 1 << 18; // node-id span of a node's neighbourhood
 
@@ -96,10 +96,13 @@ struct rpim_plan {
   float* dphi32 = nullptr;       // [sum_n][3] (mixed precision)
 
   // kept factors (keep_factors = 1)
-  int64_t* lu_off = nullptr;     // [G+1] offsets in doubles: N_g * N_g per point
+  // per point, 2 N^2 doubles at lu_off[g]: the multipliers column-major by original
+  // row (L[k*N + r] = multiplier of row r at step k), then U by position, column-major
+  // (U[c*N + p] = u_pc, c >= p); piv holds the original row pivoted at each step.
+  int64_t* lu_off = nullptr;     // [G+1]
   int64_t lu_doubles = 0;
-  double* lu = nullptr;          // [lu_doubles] rows in pivoted order
-  int32_t* piv = nullptr;        // [sum_n + 4G] pivot rows, per point at 4g + gp_ptr[g]
+  double* lu = nullptr;          // [lu_doubles]
+  int32_t* piv = nullptr;        // [sum_n + 4G] per point at 4g + gp_ptr[g]
   double* gam = nullptr;         // [3 * (sum_n + 4G)] full solutions gamma_k per point
   bool have_factors = false;
 

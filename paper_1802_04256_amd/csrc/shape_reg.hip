@@ -1,27 +1,25 @@
 // Moment-matrix solve with rows held in registers (gfx950).
 //
 // One workgroup of 64*WAVES threads per Gauss point; thread t owns row t of
-// the augmented moment matrix [G | r_0 r_1 r_2] in VGPRs: NMAX doubles of
-// matrix columns (columns n+4..NMAX-1 are zero padding) plus 3 right-hand
-// sides.  Rows never move: partial pivoting is done on row *positions* (the
-// row order the textbook algorithm has after its swaps), which yields the
-// same pivot choices, multipliers and fma sequence as whole-row swapping:
-//   step k: pivot = active row with the largest |a_k|, ties to the smaller
-//           position; it takes position k and the row that held position k
-//           takes the pivot's old position; the pivot row is broadcast through
-//           LDS; every other active row does l = a_k / u_kk and
-//           a_j = fma(-l, u_j, a_j) for j > k.
-// Back substitution runs by position, k descending: x_k = b_k / u_kk is
-// broadcast and every row at a smaller position does b = fma(-u_rk, x_k, b).
+// the augmented moment matrix [G | r_0 r_1 r_2] as a register *window*: at
+// step k the window holds the row's columns k, k+1, ..., N-1 followed by its
+// three right-hand sides (then zeros).  Rows never move; partial pivoting is
+// done on row *positions* (the row order the textbook algorithm has after
+// its swaps), which yields the same pivot choices, multipliers and fma
+// sequence as whole-row swapping:
+//   step k: the pivot is the active row with the largest |a_k| (window
+//           element 0), ties to the smaller position; it takes position k,
+//           the row that held position k takes the pivot's old position.
+//           The pivot publishes its window through LDS; every other active
+//           row computes l = a_k / u_kk and updates-and-shifts its window in
+//           one pass: w_j <- fma(-l, u_{j+1}, w_{j+1}), so column k+1 becomes
+//           element 0.  The pivot row's window (its U row) is kept in LDS.
+// Back substitution then runs by position from the U rows in LDS, k
+// descending: x_k = b_k / u_kk, b_r = fma(-u_rk, x_k, b_r) for r < k.
 //
-// Code size stays O(NMAX): the step loop is a runtime loop; row columns are
-// updated in blocks of 8 under uniform branches, and the element of column k
-// is read or written through a switch on the (uniform) step index, so no
-// register is ever indexed dynamically.  In the block that contains column
-// k, columns < k are updated with a pivot-row value of +0, which leaves them
-// unchanged (x + (+-0) = x up to the sign of an exact-zero multiplier, which
-// nothing downstream reads).  The matrix is built through a small LDS staging
-// buffer a few rows at a time; a 76 x 79 system costs ~6 KB of LDS.
+// Every register index is static: element 0 is always the pivot column and
+// the shifted update walks the window in 4-column chunks, skipping chunks
+// past the row's end under uniform branches.  Code size is O(NMAX).
 #include <cfloat>
 #include <climits>
 
@@ -36,75 +34,79 @@ __device__ __forceinline__ void flag_error(DevStatus* st, unsigned flag, int64_t
   if (g >= 0) atomicMin(&st->first_bad, (unsigned long long)g);
 }
 
-// Wave argmax of (value desc, key asc).
-__device__ __forceinline__ void wave_argmax(double& v, int& key) {
+// Wave reductions on 32-bit values with DPP: inclusive row scans (row_shr 1, 2,
+// 4, 8), then row_bcast 15 / 31 carry the row results up to lane 63.
+template <bool kMax>
+__device__ __forceinline__ unsigned dpp_step(unsigned v, unsigned id, int ctrl_sel) {
+  unsigned o;
+  switch (ctrl_sel) {
+    case 0: o = __builtin_amdgcn_update_dpp(id, v, 0x111, 0xF, 0xF, false); break;
+    case 1: o = __builtin_amdgcn_update_dpp(id, v, 0x112, 0xF, 0xF, false); break;
+    case 2: o = __builtin_amdgcn_update_dpp(id, v, 0x114, 0xF, 0xF, false); break;
+    case 3: o = __builtin_amdgcn_update_dpp(id, v, 0x118, 0xF, 0xF, false); break;
+    case 4: o = __builtin_amdgcn_update_dpp(id, v, 0x142, 0xA, 0xF, false); break;
+    default: o = __builtin_amdgcn_update_dpp(id, v, 0x143, 0xC, 0xF, false); break;
+  }
+  return kMax ? (o > v ? o : v) : (o < v ? o : v);
+}
+
+template <bool kMax>
+__device__ __forceinline__ unsigned wave_reduce_u32(unsigned v) {
+  const unsigned id = kMax ? 0u : 0xFFFFFFFFu;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double v2 = __shfl_xor(v, o, 64);
-    const int k2 = __shfl_xor(key, o, 64);
-    const bool take = (v2 > v) || (v2 == v && k2 < key);
-    v = take ? v2 : v;
-    key = take ? k2 : key;
-  }
+  for (int i = 0; i < 6; ++i) v = dpp_step<kMax>(v, id, i);
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
-#define RPIM_C8(b, X) X(b + 0) X(b + 1) X(b + 2) X(b + 3) X(b + 4) X(b + 5) X(b + 6) X(b + 7)
-#define RPIM_C128(X)                                                                                      \
-  RPIM_C8(0, X) RPIM_C8(8, X) RPIM_C8(16, X) RPIM_C8(24, X) RPIM_C8(32, X) RPIM_C8(40, X) RPIM_C8(48, X) \
-  RPIM_C8(56, X) RPIM_C8(64, X) RPIM_C8(72, X) RPIM_C8(80, X) RPIM_C8(88, X) RPIM_C8(96, X) RPIM_C8(104, X) \
-  RPIM_C8(112, X) RPIM_C8(120, X)
+// Wave argmax of |x| over active lanes (value desc, key asc), exact on the
+// bit pattern of the non-negative double; returns the value (-1 if none) and
+// the winning key.
+__device__ __forceinline__ void wave_argmax(double ax, bool active, unsigned key, double* best, unsigned* bkey) {
+  const unsigned long long bits = __double_as_longlong(ax);
+  const unsigned hi = active ? (unsigned)(bits >> 32) : 0u;
+  const unsigned lo = (unsigned)bits;
+  const unsigned mhi = wave_reduce_u32<true>(hi);
+  const unsigned mlo = wave_reduce_u32<true>((active && hi == mhi) ? lo : 0u);
+  const bool cand = active && hi == mhi && lo == mlo;
+  const unsigned mkey = wave_reduce_u32<false>(cand ? key : 0xFFFFFFFFu);
+  *bkey = mkey;
+  *best = (mkey == 0xFFFFFFFFu) ? -1.0 : __longlong_as_double(((unsigned long long)mhi << 32) | mlo);
+}
 
-// a[k] for a uniform k (jump on k; each case reads one fixed register).
-template <int NMAX>
-__device__ __forceinline__ double get_col(const double (&a)[NMAX], int k) {
-  double v = 0.0;
-  switch (k) {
-#define RPIM_GET(c)                         \
-  case (c):                                 \
-    if constexpr ((c) < NMAX) v = a[(c)];   \
-    break;
-    RPIM_C128(RPIM_GET)
-#undef RPIM_GET
-    default:
-      break;
-  }
-  return v;
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+  double b;
+  unsigned k;
+  wave_argmax(x, true, 0u, &b, &k);
+  return b;
 }
 
 template <int NMAX>
-__device__ __forceinline__ void set_col(double (&a)[NMAX], int k, double v) {
-  switch (k) {
-#define RPIM_SET(c)                         \
-  case (c):                                 \
-    if constexpr ((c) < NMAX) a[(c)] = v;   \
-    break;
-    RPIM_C128(RPIM_SET)
-#undef RPIM_SET
-    default:
-      break;
-  }
+constexpr int u_size() {
+  return NMAX * (NMAX + 7) / 2 + 8;  // sum over positions of (N + 3 - k), N <= NMAX
 }
 
 template <int NMAX, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
+__global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr, const int32_t* gp_nbr,
     const int64_t* blk_ptr, const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* R,
     const double* X, const double* gp_xyz, double C2, double q, double* dphi, int keep, const int64_t* lu_off,
     double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
   constexpr int T = 64 * WAVES;
-  constexpr int NB = NMAX / 8;
-  constexpr int WC = NMAX + 3;  // staging row width: matrix + 3 right-hand sides
-  constexpr int CH = 16;        // staging rows per chunk
-  static_assert(T >= NMAX && NMAX % 8 == 0 && NMAX <= 128, "shape");
-  __shared__ double stage[CH][WC];
-  __shared__ __align__(16) double prow[2][WAVES][NMAX];  // candidate pivot rows (zeros at columns < k)
-  __shared__ double prhs[2][WAVES][3];
+  constexpr int WC = NMAX + 4;   // window: matrix columns + 3 right-hand sides + 1 zero
+  constexpr int NCH = WC / 4;    // 4-column chunks
+  constexpr int BLK = NMAX <= 72 ? 32 : (NMAX <= 96 ? 16 : 8);  // update block (register budget)
+  constexpr int NBLK = (WC + BLK - 1) / BLK;
+  constexpr int CH = 16;         // staging rows per chunk of the build
+  constexpr int US = u_size<NMAX>();
+  constexpr int LDSD = (CH * WC > US) ? CH * WC : US;
+  static_assert(T >= NMAX && NMAX % 8 == 0, "shape");
+  __shared__ __align__(16) double lds[LDSD];            // build staging, then the U rows
+  __shared__ __align__(16) double prow[2][WAVES][NBLK * BLK];  // candidate windows shifted by one: prow[j] = w[j+1]
   __shared__ double cval[2][WAVES];
-  __shared__ double cpiv[2][WAVES];
-  __shared__ int ckey[2][WAVES];
+  __shared__ double cpiv[2][WAVES];                     // candidate's w[0]
+  __shared__ unsigned ckey[2][WAVES];
   __shared__ double xsol[3][NMAX];
   __shared__ int S[NMAX];
-  __shared__ int ipiv[NMAX];
   __shared__ int rowat[NMAX];
   __shared__ double xg[3];
   __shared__ double rmax[WAVES];
@@ -129,11 +131,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
   }
   __syncthreads();
 
-  // ---- build rows through the staging buffer --------------------------------
-  double a[NMAX];
-  double b[3] = {0.0, 0.0, 0.0};
+  // ---- build rows (columns 0..N-1, then the 3 right-hand sides) ------------------
+  double a[WC];
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j) a[j] = 0.0;
+  for (int j = 0; j < WC; ++j) a[j] = 0.0;
+  double* stage = lds;
   for (int r0 = 0; r0 < N; r0 += CH) {
     for (int idx = t; idx < CH * WC; idx += T) {
       const int rr = idx / WC, c = idx - rr * WC;
@@ -146,36 +148,34 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
           v = 1.0;
         } else if (c < N) {
           v = X[3 * (int64_t)S[r] + (c - n - 1)] - xg[c - n - 1];
-        } else if (c >= NMAX) {
-          v = coefs[r] * (xg[c - NMAX] - X[3 * (int64_t)S[r] + (c - NMAX)]);
+        } else if (c < N + 3) {
+          v = coefs[r] * (xg[c - N] - X[3 * (int64_t)S[r] + (c - N)]);
         }
       } else if (r == n) {
         v = c < n ? 1.0 : 0.0;
       } else if (r < N) {
         const int k = r - n - 1;
         if (c < n) v = X[3 * (int64_t)S[c] + k] - xg[k];
-        else if (c == NMAX + k) v = 1.0;
+        else if (c == N + k) v = 1.0;
       }
-      stage[rr][c] = v;
+      stage[rr * WC + c] = v;
     }
     __syncthreads();
     if (t >= r0 && t < r0 + CH && t < N) {
 #pragma unroll
-      for (int j = 0; j < NMAX; ++j) a[j] = stage[t - r0][j];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) b[j] = stage[t - r0][NMAX + j];
+      for (int j = 0; j < WC; ++j) a[j] = stage[(t - r0) * WC + j];
     }
     __syncthreads();
   }
   if (hard) flag_error(st, kFlagPow, g);
 
-  // singularity threshold N * eps * max|G|
+  // singularity threshold N * eps * max|G| (the right-hand sides excluded)
   double mx = 0.0;
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j) mx = fmax(mx, fabs(a[j]));
+  for (int j = 0; j < NMAX; ++j)
+    if (j < N) mx = fmax(mx, fabs(a[j]));
   {
-    int dummy = 0;
-    wave_argmax(mx, dummy);
+    mx = wave_max_nonneg(mx);
     if (lane == 0) rmax[w] = mx;
     __syncthreads();
     mx = rmax[0];
@@ -184,34 +184,29 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
   }
   const double tiny = ((double)N * DBL_EPSILON) * mx;
 
-  // ---- LU with partial pivoting on positions ----------------------------------
+  // ---- LU with partial pivoting on positions; windows shift each step ----------
   int pos = t;              // current position of my row
   const bool real = t < N;  // padding rows never take part
+  double* Lkeep = keep ? lu + lu_off[g] : nullptr;      // multipliers, column-major by original row
+  int uoff = 0;                                           // offset of U row k in lds
 #pragma unroll 1
   for (int k = 0; k < N; ++k) {
     const int buf = k & 1;
-    const int kb = k >> 3;  // block holding column k
+    const int len = N + 3 - k;  // window elements in use (columns k..N-1 and 3 rhs)
     const bool active = real && pos >= k;
-    const double ak = get_col<NMAX>(a, k);
-    double v = active ? fabs(ak) : -1.0;
-    int key = active ? (pos << 8) | t : INT_MAX;
-    wave_argmax(v, key);
-    // the wave's candidate publishes its row (zeros at columns < k)
-    if ((key & 255) == t) {
+    double v;
+    unsigned key;
+    wave_argmax(fabs(a[0]), active, ((unsigned)pos << 8) | (unsigned)t, &v, &key);
+    if ((key & 255u) == (unsigned)t) {  // this wave's candidate publishes its window
 #pragma unroll
-      for (int bb = 0; bb < NB; ++bb) {
-        if (bb == kb) {
+      for (int c = 0; c < NCH; ++c) {
+        if (4 * c < len) {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) prow[buf][w][8 * bb + e] = (8 * bb + e > k) ? a[8 * bb + e] : 0.0;
-        } else if (bb > kb && 8 * bb < N) {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) prow[buf][w][8 * bb + e] = a[8 * bb + e];
+          for (int e = 0; e < 4; ++e)
+            if (4 * c + e + 1 < WC) prow[buf][w][4 * c + e] = a[4 * c + e + 1];
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
-#pragma unroll
-      for (int j = 0; j < 3; ++j) prhs[buf][w][j] = b[j];
-      cpiv[buf][w] = ak;
+      cpiv[buf][w] = a[0];
     }
     if (lane == 0) {
       cval[buf][w] = v;
@@ -219,59 +214,84 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
     }
     __syncthreads();
     double best = cval[buf][0];
-    int bkey = ckey[buf][0];
+    unsigned bkey = ckey[buf][0];
     int bw = 0;
 #pragma unroll
     for (int i = 1; i < WAVES; ++i) {
       const double v2 = cval[buf][i];
-      const int k2 = ckey[buf][i];
+      const unsigned k2 = ckey[buf][i];
       if (v2 > best || (v2 == best && k2 < bkey)) { best = v2; bkey = k2; bw = i; }
     }
     if (!(best > tiny)) {
       if (t == 0) flag_error(st, kFlagSingular, g);
       return;  // uniform: every thread saw the same best
     }
-    const int prow_id = bkey & 255, ppos = bkey >> 8;
-    if (t == 0) {
-      ipiv[k] = ppos;
-      rowat[k] = prow_id;
-    }
+    const int prow_id = (int)(bkey & 255u), ppos = (int)(bkey >> 8);
+    const double* u = prow[buf][bw];  // u[j] = pivot column k+1+j
+    const double ukk = cpiv[buf][bw];
+    // keep the pivot window as U row k
+    if (t == 0) lds[uoff] = ukk;
+    for (int i = t; i < len - 1; i += T) lds[uoff + 1 + i] = u[i];
+    if (t == 0) rowat[k] = prow_id;
     if (t == prow_id) pos = k;
     else if (pos == k) pos = ppos;
     if (real && pos > k) {
-      const double l = ak / cpiv[buf][bw];
-      const double* u = prow[buf][bw];
+      const double l = a[0] / ukk;
+      if (keep) Lkeep[(int64_t)k * N + t] = l;
+      // update and shift: element j takes column k+1+j.  Blocks of BLK columns:
+      // all of a block's pivot-row loads are in flight before its first fma.
 #pragma unroll
-      for (int bb = 0; bb < NB; ++bb) {
-        if (bb >= kb && 8 * bb < N) {
+      for (int c = 0; c < NBLK; ++c) {
+        if (BLK * c < len) {
+          double uu[BLK];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a[8 * bb + e] = __builtin_fma(-l, u[8 * bb + e], a[8 * bb + e]);
+          for (int e = 0; e < BLK; e += 2) {
+            if (BLK * c + e < WC) {
+              const double2 v2 = *reinterpret_cast<const double2*>(u + BLK * c + e);
+              uu[e] = v2.x;
+              uu[e + 1] = v2.y;
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < BLK; ++e) {
+            const int j = BLK * c + e;
+            if (j + 1 < WC) a[j] = __builtin_fma(-l, uu[e], a[j + 1]);
+            else if (j < WC) a[j] = 0.0;
+          }
         }
-        __builtin_amdgcn_sched_barrier(0);  // keep each block's loads next to its fmas
       }
-      set_col<NMAX>(a, k, l);  // column k holds the multiplier (u_k was 0 above)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) b[j] = __builtin_fma(-l, prhs[buf][bw][j], b[j]);
     }
+    uoff += len;
   }
   __syncthreads();
 
-  // ---- back substitution by position, k descending ----------------------------
+  // ---- back substitution by position from the U rows, k descending ------------
+  // thread r holds b_r (the right-hand sides of U row r)
+  int my_off = 0;
+  double bb[3] = {0.0, 0.0, 0.0};
+  if (t < N) {
+    my_off = t * (N + 3) - (t * (t - 1)) / 2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) bb[j] = lds[my_off + (N - t) + j];
+  }
+  int koff = (N - 1) * (N + 3) - ((N - 1) * (N - 2)) / 2;
 #pragma unroll 1
   for (int k = N - 1; k >= 0; --k) {
-    const double ak = get_col<NMAX>(a, k);
-    if (t == rowat[k]) {
+    if (t == k) {
+      const double ukk = lds[koff];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        b[j] = b[j] / ak;
-        xsol[j][k] = b[j];
+        bb[j] = bb[j] / ukk;
+        xsol[j][k] = bb[j];
       }
     }
     __syncthreads();
-    if (real && pos < k) {
+    if (t < k) {
+      const double urk = lds[my_off + (k - t)];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) b[j] = __builtin_fma(-ak, xsol[j][k], b[j]);
+      for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, xsol[j][k], bb[j]);
     }
+    koff -= (N + 3 - (k - 1));
   }
   __syncthreads();
 
@@ -281,14 +301,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
     dphi[3 * (b0 + aa) + j] = xsol[j][aa];
   }
   if (keep) {
-    double* L = lu + lu_off[g];  // column-major by position
-    if (real) {
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c)
-        if (c < N) L[(int64_t)c * N + pos] = a[c];
+    // U by position, column-major (U[c*N + p] = u_pc), after the multipliers
+    double* U = Lkeep + (int64_t)N * N;
+    for (int k = 0; k < N; ++k) {
+      const int off = k * (N + 3) - (k * (k - 1)) / 2;
+      for (int j = t; j < N - k; j += T) U[(int64_t)(k + j) * N + k] = lds[off + j];
     }
     const int64_t o = b0 + 4 * g;
-    for (int i = t; i < N; i += T) piv_out[o + i] = ipiv[i];
+    for (int i = t; i < N; i += T) piv_out[o + i] = rowat[i];
     for (int idx = t; idx < 3 * N; idx += T) {
       const int j = idx / N, i = idx - j * N;
       gam[3 * o + idx] = xsol[j][i];
@@ -298,7 +318,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_reg(
 
 template <int NMAX, int WAVES>
 rpim_status launch_one(rpim_plan* p, const Bucket& bk, const double* X, double C2, int keep, hipStream_t s) {
-  hipLaunchKernelGGL((k_shape_reg<NMAX, WAVES>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
+  hipLaunchKernelGGL((k_shape_win<NMAX, WAVES>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
                      (const int32_t*)p->gp_order, bk.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
                      (const int64_t*)p->blk_ptr, (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off,
                      (const uint2*)p->rbm, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, p->dphi,
