@@ -82,7 +82,7 @@ __device__ __forceinline__ double wave_max_nonneg(double x) {
 
 template <int NMAX>
 constexpr int u_size() {
-  return NMAX * (NMAX + 7) / 2 + 8;  // sum over positions of (N + 3 - k), N <= NMAX
+  return NMAX * (NMAX + 7) / 2 + 8;  // sum over positions k < N <= NMAX of (NMAX + 3 - k)
 }
 
 template <int NMAX, int WAVES>
@@ -96,17 +96,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   constexpr int NCH = WC / 4;    // 4-column chunks
   constexpr int BLK = NMAX <= 72 ? 32 : (NMAX <= 96 ? 16 : 8);  // update block (register budget)
   constexpr int NBLK = (WC + BLK - 1) / BLK;
-  constexpr int CH = 16;         // staging rows per chunk of the build
   constexpr int US = u_size<NMAX>();
-  constexpr int LDSD = (CH * WC > US) ? CH * WC : US;
+  constexpr int LDSD = US;
   static_assert(T >= NMAX && NMAX % 8 == 0, "shape");
-  __shared__ __align__(16) double lds[LDSD];            // build staging, then the U rows
+  __shared__ __align__(16) double lds[LDSD];            // the U rows
   __shared__ __align__(16) double prow[2][WAVES][NBLK * BLK];  // candidate windows shifted by one: prow[j] = w[j+1]
   __shared__ double cval[2][WAVES];
   __shared__ double cpiv[2][WAVES];                     // candidate's w[0]
   __shared__ unsigned ckey[2][WAVES];
   __shared__ double xsol[3][NMAX];
   __shared__ int S[NMAX];
+  __shared__ int rlo[NMAX];          // per support node: first id of its row window,
+  __shared__ int64_t rwb[NMAX];      // its rank-bitmap word offset,
+  __shared__ int64_t rbp[NMAX];      // and its pattern row start
+  __shared__ double xs[3 * NMAX];    // support node coordinates
   __shared__ int rowat[NMAX];
   __shared__ double xg[3];
   __shared__ double rmax[WAVES];
@@ -117,13 +120,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   const int64_t b0 = gp_ptr[g];
   const int n = (int)(gp_ptr[g + 1] - b0);
   const int N = n + 4;
-  for (int i = t; i < n; i += T) S[i] = gp_nbr[b0 + i];
+  for (int i = t; i < n; i += T) {
+    const int32_t I = gp_nbr[b0 + i];
+    S[i] = I;
+    rlo[i] = row_lo[I];
+    rwb[i] = rbm_off[I];
+    rbp[i] = blk_ptr[I];
+    for (int k = 0; k < 3; ++k) xs[3 * i + k] = X[3 * (int64_t)I + k];
+  }
   if (t < 3) xg[t] = gp_xyz[3 * g + t];
   __syncthreads();
   // derivative right-hand-side coefficients fl(fl(2q) * R) / t, one power per support node
   bool hard = false;
   for (int r = t; r < n; r += T) {
-    const double* xa = X + 3 * (int64_t)S[r];
+    const double* xa = xs + 3 * r;
     const double dx = xa[0] - xg[0], dy = xa[1] - xg[1], dz = xa[2] - xg[2];
     const double tt = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
     const double Rv = pow_cr(tt, q, &hard);
@@ -131,42 +141,46 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   }
   __syncthreads();
 
-  // ---- build rows (columns 0..N-1, then the 3 right-hand sides) ------------------
+  // ---- build: thread r fills its own row in registers ---------------------------
+  // Columns 0..N-1 of G (zero padding up to NMAX), then the three right-hand
+  // sides at NMAX..NMAX+2.  Every column index is static; the radial-basis
+  // entries of a row are n independent (rank word, value) load pairs.
   double a[WC];
+  if (t < n) {
+    const int lo_r = rlo[t];
+    const int64_t wb_r = rwb[t], bp_r = rbp[t];
+    const double xr0 = xs[3 * t], xr1 = xs[3 * t + 1], xr2 = xs[3 * t + 2];
 #pragma unroll
-  for (int j = 0; j < WC; ++j) a[j] = 0.0;
-  double* stage = lds;
-  for (int r0 = 0; r0 < N; r0 += CH) {
-    for (int idx = t; idx < CH * WC; idx += T) {
-      const int rr = idx / WC, c = idx - rr * WC;
-      const int r = r0 + rr;
+    for (int c = 0; c < NMAX; ++c) {
       double v = 0.0;
-      if (r < n) {
-        if (c < n) {
-          v = R[block_pos(blk_ptr, row_lo, rbm_off, rbm, S[r], S[c])];
-        } else if (c == n) {
-          v = 1.0;
-        } else if (c < N) {
-          v = X[3 * (int64_t)S[r] + (c - n - 1)] - xg[c - n - 1];
-        } else if (c < N + 3) {
-          v = coefs[r] * (xg[c - N] - X[3 * (int64_t)S[r] + (c - N)]);
-        }
-      } else if (r == n) {
-        v = c < n ? 1.0 : 0.0;
-      } else if (r < N) {
-        const int k = r - n - 1;
-        if (c < n) v = X[3 * (int64_t)S[c] + k] - xg[k];
-        else if (c == N + k) v = 1.0;
+      if (c < n) {
+        const int rel = S[c] - lo_r;
+        const uint2 wd = rbm[wb_r + (rel >> 5)];
+        v = R[bp_r + (int64_t)wd.y + __popc(wd.x & ((1u << (rel & 31)) - 1u))];
+      } else if (c == n) {
+        v = 1.0;
+      } else if (c < N) {
+        const int k = c - n - 1;
+        v = (k == 0 ? xr0 : (k == 1 ? xr1 : xr2)) - xg[k];
       }
-      stage[rr * WC + c] = v;
+      a[c] = v;
     }
-    __syncthreads();
-    if (t >= r0 && t < r0 + CH && t < N) {
+    const double cf = coefs[t];
+    a[NMAX] = cf * (xg[0] - xr0);
+    a[NMAX + 1] = cf * (xg[1] - xr1);
+    a[NMAX + 2] = cf * (xg[2] - xr2);
+  } else if (t < N) {
+    const int k = t - n - 1;  // -1 for the row of ones
 #pragma unroll
-      for (int j = 0; j < WC; ++j) a[j] = stage[(t - r0) * WC + j];
-    }
-    __syncthreads();
+    for (int c = 0; c < NMAX; ++c) a[c] = c < n ? (k < 0 ? 1.0 : xs[3 * c + k] - xg[k]) : 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a[NMAX + j] = (k == j) ? 1.0 : 0.0;
+  } else {
+#pragma unroll
+    for (int c = 0; c < NMAX + 3; ++c) a[c] = 0.0;
   }
+#pragma unroll
+  for (int c = NMAX + 3; c < WC; ++c) a[c] = 0.0;
   if (hard) flag_error(st, kFlagPow, g);
 
   // singularity threshold N * eps * max|G| (the right-hand sides excluded)
@@ -192,7 +206,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
 #pragma unroll 1
   for (int k = 0; k < N; ++k) {
     const int buf = k & 1;
-    const int len = N + 3 - k;  // window elements in use (columns k..N-1 and 3 rhs)
+    const int len = NMAX + 3 - k;  // window elements in use (columns k..NMAX-1 and 3 rhs)
     const bool active = real && pos >= k;
     double v;
     unsigned key;
@@ -266,15 +280,16 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   __syncthreads();
 
   // ---- back substitution by position from the U rows, k descending ------------
-  // thread r holds b_r (the right-hand sides of U row r)
+  // U row k starts at k (NMAX + 3) - k (k - 1) / 2; its element j is column k + j
+  // and its right-hand sides sit at NMAX - k + (0, 1, 2).
   int my_off = 0;
   double bb[3] = {0.0, 0.0, 0.0};
   if (t < N) {
-    my_off = t * (N + 3) - (t * (t - 1)) / 2;
+    my_off = t * (NMAX + 3) - (t * (t - 1)) / 2;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) bb[j] = lds[my_off + (N - t) + j];
+    for (int j = 0; j < 3; ++j) bb[j] = lds[my_off + (NMAX - t) + j];
   }
-  int koff = (N - 1) * (N + 3) - ((N - 1) * (N - 2)) / 2;
+  int koff = (N - 1) * (NMAX + 3) - ((N - 1) * (N - 2)) / 2;
 #pragma unroll 1
   for (int k = N - 1; k >= 0; --k) {
     if (t == k) {
@@ -291,7 +306,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
 #pragma unroll
       for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, xsol[j][k], bb[j]);
     }
-    koff -= (N + 3 - (k - 1));
+    koff -= (NMAX + 3 - (k - 1));
   }
   __syncthreads();
 
@@ -304,7 +319,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     // U by position, column-major (U[c*N + p] = u_pc), after the multipliers
     double* U = Lkeep + (int64_t)N * N;
     for (int k = 0; k < N; ++k) {
-      const int off = k * (N + 3) - (k * (k - 1)) / 2;
+      const int off = k * (NMAX + 3) - (k * (k - 1)) / 2;
       for (int j = t; j < N - k; j += T) U[(int64_t)(k + j) * N + k] = lds[off + j];
     }
     const int64_t o = b0 + 4 * g;
