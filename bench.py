@@ -30,6 +30,14 @@ METRIC = "Gauss pts assembled/s + HBM GB/s, plain FP64 vs mixed/batched; bwd/fwd
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
+# HBM bytes moved by all moment-matrix kernel launches (k_shape*) of one step: FETCH_SIZE and WRITE_SIZE
+# counter runs of this script, each scaled by what the same counter reads for a plain 1 GiB device copy
+# (fetch x2.000, write x1.000).  The summary and its commands are in profiles/.  The figure belongs to
+# the kernel sources it was measured on: any change to them reports traffic as null until re-measured.
+SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/assemble.hip",
+                 "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
+SHAPE_TRAFFIC = {"sources_sha256": "8abb461089a2b3d64f891d1dc3930d6e0f31e805df4bd2b5ff7d257230abc6e5", "bytes_per_step": 3.926e10}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -40,6 +48,16 @@ def shape_flops(n):
     import numpy as np
     N = n.astype(np.float64) + 4.0
     return float(np.sum(2.0 / 3.0 * N ** 3 + 6.0 * N ** 2))
+
+
+def shape_traffic():
+    """Measured HBM bytes per step of the moment-matrix kernels, or None if their sources changed since."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SHAPE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return SHAPE_TRAFFIC["bytes_per_step"] if h.hexdigest() == SHAPE_TRAFFIC["sources_sha256"] else None
 
 
 def cpu_baseline(prob, n_sample, n_vec=8):
@@ -78,6 +96,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2700, help="Gauss points in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the assembly-only / mixed measurements")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="before the steps, run one device fill and one device copy of this many MiB "
+                         "(a known-size reference for the HBM byte counters of a profiler)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -112,6 +133,15 @@ def main():
     Xh = prob.node_xyz
     fixed = np.where(Xh[:, 2] == Xh[:, 2].min())[0]
     fixed = torch.from_numpy(np.sort((3 * fixed[:, None] + np.arange(3)).ravel()).astype(np.int32)).to(dev)
+
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy calibration: fill {nbytes} B, copy {nbytes} B -> {nbytes} B")
 
     def step():
         plan.rebuild_pattern(X)
@@ -165,7 +195,7 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "roofline": {"kernel": "k_shape (moment matrix + LU + 3 solves, all buckets)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": shape_traffic(),
                      "flops_per_step": flops, "launches_per_step": info["n_buckets"],
                      "ms_per_step": shape_ms},
     }
