@@ -60,6 +60,126 @@ def shape_traffic():
     return SHAPE_TRAFFIC["bytes_per_step"] if h.hexdigest() == SHAPE_TRAFFIC["sources_sha256"] else None
 
 
+def csr_operator(row_ptr, col_idx, vals):
+    """x -> K x for a CSR matrix on the GPU, in float64 (float32 values are widened exactly)."""
+    import torch
+    n = row_ptr.numel() - 1
+    A = torch.sparse_csr_tensor(row_ptr, col_idx.to(torch.int64), vals.to(torch.float64), size=(n, n))
+    return lambda x: torch.mv(A, x)
+
+
+def pcg(A, b, dinv, rtol, maxit=50000):
+    """Jacobi-preconditioned conjugate gradients; returns (x, iterations, relative residual)."""
+    import torch
+    x = torch.zeros_like(b)
+    r = b.clone()
+    z = dinv * r
+    p = z.clone()
+    rz = torch.dot(r, z)
+    bn = float(torch.linalg.norm(b))
+    it, rel = 0, 1.0
+    for it in range(1, maxit + 1):
+        Ap = A(p)
+        alpha = rz / torch.dot(p, Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        rel = float(torch.linalg.norm(r)) / bn
+        if rel <= rtol:
+            break
+        z = dinv * r
+        rz_new = torch.dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, it, rel
+
+
+def displacement_error(prob, row_ptr, col_idx, K64, K32, factor=1e8):
+    """Relative displacement error of the mixed-precision K after a solve.
+
+    Base nodes fixed by the penalty method (as in the benchmark step), a unit
+    downward force on every node of the top surface.  u64 solves K64 u = f;
+    since K32 u32 = f, u32 - u64 = K32^-1 (K64 - K32) u64 exactly, which is
+    solved directly (its accuracy then does not depend on how far u64 is
+    converged).  K64 and K32 are modified in place by the penalty update."""
+    import numpy as np
+    import torch
+    import paper_1802_04256_amd as rp
+    dev = K64.device
+    X = prob.node_xyz
+    base = np.where(X[:, 2] == X[:, 2].min())[0]
+    fixed = torch.from_numpy(np.sort((3 * base[:, None] + np.arange(3)).ravel()).astype(np.int32)).to(dev)
+    rp.apply_penalty_bc(row_ptr, col_idx, K64, fixed, factor=factor)
+    rp.apply_penalty_bc(row_ptr, col_idx, K32, fixed, factor=factor)
+    top = np.where(X[:, 2] == X[:, 2].max())[0]
+    f = torch.zeros(3 * prob.n_nodes, dtype=torch.float64, device=dev)
+    f[torch.from_numpy(3 * top + 2).to(dev)] = -1.0
+    rows = torch.repeat_interleave(torch.arange(3 * prob.n_nodes, device=dev), torch.diff(row_ptr))
+    diag = torch.zeros_like(f).index_add_(0, rows, torch.where(rows == col_idx.long(), K64, 0.0))
+    del rows
+    A64 = csr_operator(row_ptr, col_idx, K64)
+    A32 = csr_operator(row_ptr, col_idx, K32)
+    u64, it64, res64 = pcg(A64, f, 1.0 / diag, 1e-10)
+    d = A64(u64) - A32(u64)
+    du, it32, res32 = pcg(A32, d, 1.0 / diag, 1e-6)
+    return {"u_rel_err": float(torch.linalg.norm(du) / torch.linalg.norm(u64)), "cg_iters": [it64, it32],
+            "cg_rel_residual": [res64, res32],
+            "load": "unit downward force on each top-surface node; base fixed by penalty 1e8 x max diag"}
+
+
+def batched_leg(plain_fp64_gp_s):
+    """64 independent jittered slopes (log-uniform 1k-30k nodes) in one plan: one HIP graph holding the
+    whole mixed-precision assembly (pair table, one launch per support-size bucket, row gather), replayed;
+    the same batch assembled eagerly in FP64 beside it."""
+    import numpy as np
+    import torch
+
+    import paper_1802_04256_amd as rp
+    import workloads as W
+    dev = torch.device("cuda:0")
+    prob = W.named("batch64")
+    log(f"batched: models={prob.n_models} nodes={prob.n_nodes} gps={prob.n_gp}")
+    plan = rp.Plan.from_problem(prob, device=dev)
+    plan.build_pattern()
+    info = plan.info()
+    X = torch.from_numpy(prob.node_xyz).to(dev)
+    E = torch.from_numpy(prob.cell_E).to(dev)
+    K32 = torch.empty(plan.nnz, dtype=torch.float32, device=dev)
+    plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
+    torch.cuda.synchronize()
+    plan.status()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
+
+    def timed(fn, reps=3):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - a)
+        return float(np.median(ts))
+    t_graph = timed(graph.replay)
+    del graph
+    K64 = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    plan.assemble(X, E, prob.nu, rp.FP64, out=K64)
+    t_fp64 = timed(lambda: plan.assemble(X, E, prob.nu, rp.FP64, out=K64))
+    plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
+    err = float(torch.linalg.norm(K32.double() - K64) / torch.linalg.norm(K64))
+    plan.status()
+    res = {"workload": "64 jittered slopes, log-uniform 1k-30k nodes (seed 4), lognormal E, one block-diagonal plan",
+           "n_models": prob.n_models, "n_nodes": prob.n_nodes, "n_gp": prob.n_gp, "nnz": info["nnz"],
+           "sum_n": info["sum_n"], "buckets": info["n_buckets"],
+           "ms": {"mixed_graph": t_graph * 1e3, "fp64_eager": t_fp64 * 1e3},
+           "gp_per_s": {"mixed_graph": prob.n_gp / t_graph, "fp64_eager": prob.n_gp / t_fp64},
+           "mixed_rel_fro_err": err}
+    if plain_fp64_gp_s:
+        res["mixed_graph_vs_plain_fp64_slope"] = res["gp_per_s"]["mixed_graph"] / plain_fp64_gp_s
+    log(f"batched: mixed graph {t_graph * 1e3:.1f} ms, fp64 {t_fp64 * 1e3:.1f} ms, err {err:.2e}")
+    return res
+
+
 def cpu_baseline(prob, n_sample, n_vec=8):
     """Oracle (serial, one core) on the first n_sample Gauss points of the workload:
     pattern, FP64 assembly, penalty and adjoint, scaled to Gauss points per second."""
@@ -96,6 +216,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2700, help="Gauss points in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the assembly-only / mixed measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-model batched assembly")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="before the steps, run one device fill and one device copy of this many MiB "
                          "(a known-size reference for the HBM byte counters of a profiler)")
@@ -225,6 +346,10 @@ def main():
                               "backward": t_bwd * 1e3, "pattern": t_pat * 1e3}
         out["bwd_fwd"] = t_bwd / t_fwd_keep
         out["mixed_rel_fro_err"] = err32
+        plan.assemble(X, E, prob.nu, rp.FP64, out=Kout)
+        out["mixed_displacement"] = displacement_error(prob, plan.row_ptr, plan.col_idx, Kout, K32)
+        log(f"mixed displacement error {out['mixed_displacement']['u_rel_err']:.3e} "
+            f"(CG iterations {out['mixed_displacement']['cg_iters']})")
         # algorithmic HBM bytes of one FP64 assembly: K values written once, dphi written
         # and read once, supports / inverse lists / pattern read once
         sum_n = info["sum_n"]
@@ -232,6 +357,9 @@ def main():
         out["hbm_gbps_fp64_assembly"] = alg_bytes / t_fp64 / 1e9
         log(f"assemble fp64 {t_fp64 * 1e3:.2f} ms, mixed {t_mixed * 1e3:.2f} ms (err {err32:.2e}), "
             f"bwd {t_bwd * 1e3:.2f} ms, bwd/fwd {out['bwd_fwd']:.2f}")
+
+    if not args.no_extras and not args.no_batched:
+        out["batched"] = batched_leg(out.get("assemble_gp_per_s", {}).get("fp64"))
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")

@@ -93,8 +93,9 @@ class OracleModel:
         self.sum_n = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orcl_model_destroy(self.h)
+        h = getattr(self, "h", None)
+        if h and lib is not None:  # module globals may already be gone at interpreter exit
+            lib().orcl_model_destroy(h)
             self.h = None
 
     def build_pattern(self):

@@ -247,9 +247,10 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
   for (int i = tid; i < nw; i += kGatherThreads) bm[i] = rbm[wb + i];
   for (int i = tid; i < 9 * L; i += kGatherThreads) acc[i] = 0.0;
   __syncthreads();
-  // Two-stage software pipeline over the row's Gauss points: point metadata
-  // (scalar) is fetched two points ahead, the per-lane support entries one
-  // point ahead, so the dependent global loads overlap the accumulation.
+  // Software pipeline over the row's Gauss points: point metadata (scalar) is
+  // fetched three points ahead, the per-lane support entries two points
+  // ahead, so the dependent global loads overlap the accumulation.  Loads past
+  // the row's last point re-read the last point (no branch around a load).
   struct Meta {
     int64_t b0;
     int n, aI;
@@ -279,28 +280,27 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const int b = lane + 64 * s2;
-      l.J[s2] = -1;
-      if (b < m.n) {
-        l.J[s2] = gp_nbr[m.b0 + b];
-        for (int k = 0; k < 3; ++k) l.pJ[s2][k] = dphi[3 * (m.b0 + b) + k];
-      } else {
-        for (int k = 0; k < 3; ++k) l.pJ[s2][k] = 0.0;
-      }
+      const int bc = b < m.n ? b : m.n - 1;  // lanes past the support re-read its last entry
+      const int32_t J = gp_nbr[m.b0 + bc];
+      l.J[s2] = b < m.n ? J : -1;
+      for (int k = 0; k < 3; ++k) l.pJ[s2][k] = dphi[3 * (m.b0 + bc) + k];
     }
     return l;
   };
-  Meta m_cur = {}, m_nxt = {};
-  Lanes l_cur = {};
+  const int64_t e_last = e_end - 1;
+  auto clampe = [&](int64_t e) { return e < e_last ? e : e_last; };
+  Meta m_cur = {}, m_nxt = {}, m_n2 = {};
+  Lanes l_cur = {}, l_nxt = {};
   if (e_beg < e_end) {
     m_cur = meta(e_beg);
+    m_nxt = meta(clampe(e_beg + 1));
     l_cur = lanes(m_cur);
+    m_n2 = meta(clampe(e_beg + 2));
+    l_nxt = lanes(m_nxt);
   }
-  if (e_beg + 1 < e_end) m_nxt = meta(e_beg + 1);
   for (int64_t e = e_beg; e < e_end; ++e) {
-    Meta m_nn = {};
-    if (e + 2 < e_end) m_nn = meta(e + 2);
-    Lanes l_nxt = {};
-    if (e + 1 < e_end) l_nxt = lanes(m_nxt);
+    const Meta m_n3 = meta(clampe(e + 3));
+    const Lanes l_n2 = lanes(m_n2);
     const double lc = m_cur.lc, mc = m_cur.mc;
     const double pI0 = l_cur.pI[0], pI1 = l_cur.pI[1], pI2 = l_cur.pI[2];
     // this wave's component alpha of phi_I (no dynamic register indexing)
@@ -351,8 +351,10 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
       accum(gp_nbr[eb], dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]);
     }
     m_cur = m_nxt;
+    m_nxt = m_n2;
+    m_n2 = m_n3;
     l_cur = l_nxt;
-    m_nxt = m_nn;
+    l_nxt = l_n2;
   }
   __syncthreads();
   const int64_t base = 9 * rb;
@@ -365,6 +367,17 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Raise a kernel's dynamic-LDS limit only when a launch needs more than was
+// set before, so launches recorded into a graph make no attribute calls once
+// the plan has run eagerly.
+rpim_status lds_limit(const void* fn, size_t lds, size_t* cur) {
+  if (lds <= *cur) return RPIM_OK;
+  RPIM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  *cur = lds;
+  return RPIM_OK;
+}
+size_t g_lds_shape = 0, g_lds_gather64 = 0, g_lds_gather32 = 0;
 
 }  // namespace
 
@@ -393,7 +406,7 @@ rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s)
     const int ld = ((N + 3) | 1);  // odd row stride in doubles
     const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
     if (lds > 160 * 1024) return RPIM_E_RANGE;
-    RPIM_HIP(hipFuncSetAttribute((const void*)k_shape, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (rpim_status st = lds_limit((const void*)k_shape, lds, &g_lds_shape)) return st;
     hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
                        b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
@@ -413,16 +426,14 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds > 160 * 1024) return RPIM_E_RANGE;
   if (precision == RPIM_FP64) {
-    RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
+    if (rpim_status st = lds_limit((const void*)k_rowgather<false>, lds, &g_lds_gather64)) return st;
     hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                        (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
   } else {
-    RPIM_HIP(hipFuncSetAttribute((const void*)k_rowgather<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
+    if (rpim_status st = lds_limit((const void*)k_rowgather<true>, lds, &g_lds_gather32)) return st;
     hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,

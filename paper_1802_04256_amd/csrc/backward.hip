@@ -54,8 +54,8 @@ __global__ void k_symmetrize(int64_t nblk, const int64_t* blk_ptr, const int32_t
 }
 
 // Row gather: Phibar and dE share for each slot (g, a_I), I = blockIdx.x.
-// Slots are independent, so each wave takes its own Gauss points (lanes over
-// the support) and reduces within the wave: no barriers after the row load.
+// Slots are independent, so each wave takes its own Gauss points and reduces
+// within the wave: no barriers after the row load.
 __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const int32_t* row_lo,
                                                  const int64_t* rbm_off, const uint2* rbm,
                                                  const int64_t* inv_ptr, const uint64_t* inv_key,
@@ -78,44 +78,56 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
     Mrow[idx] = M[9 * rb + 3 * (int64_t)al * L + 3 * pos + be];
   }
   __syncthreads();
-  for (int64_t e = inv_ptr[I] + wv; e < inv_ptr[I + 1]; e += kT / 64) {
-    const uint64_t key = inv_key[e];
-    const int64_t g = (int64_t)(key >> 8);
-    const int aI = (int)(key & 255);
-    const int64_t b0 = gp_ptr[g];
-    const int n = (int)(gp_ptr[g + 1] - b0);
-    const double w = wdet[g];
-    const double c = w * E[gp_cell[g]];
-    const double lc = c * lam, mc = c * mu;
-    const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
+  // Each wave takes four slots at a time, sixteen lanes per slot (lanes over
+  // the support of the slot's point), so four independent chains of dependent
+  // loads are in flight per wave.
+  const int q = lane >> 4, ql = lane & 15;
+  const int64_t e_end = inv_ptr[I + 1];
+  for (int64_t eb = inv_ptr[I] + 4 * wv; eb < e_end; eb += kT / 16) {
+    const int64_t e = eb + q;
+    const bool live = e < e_end;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = lane; b < n; b += 64) {
-      const int32_t J = gp_nbr[b0 + b];
-      const int r = J - lo_I;
-      const uint2 bw = bm[r >> 5];
-      const int pos = (int)bw.y + __popc(bw.x & ((1u << (r & 31)) - 1u));
-      const double* Mb = Mrow + 9 * pos;
-      const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
-      const double tr = Mb[0] + Mb[4] + Mb[8];
-      for (int ga = 0; ga < 3; ++ga) {
-        const double s1 = Mb[3 * ga] * pb[0] + Mb[3 * ga + 1] * pb[1] + Mb[3 * ga + 2] * pb[2];
-        const double s2 = Mb[ga] * pb[0] + Mb[3 + ga] * pb[1] + Mb[6 + ga] * pb[2];
-        v[ga] += lc * s1 + mc * s2 + mc * tr * pb[ga];
-      }
-      const double dot = pI[0] * pb[0] + pI[1] * pb[1] + pI[2] * pb[2];
-      double kk = 0.0;
-      for (int al = 0; al < 3; ++al)
-        for (int be = 0; be < 3; ++be) {
-          const double kv = lam * pI[al] * pb[be] + mu * pI[be] * pb[al] + (al == be ? mu * dot : 0.0);
-          kk += Mb[3 * al + be] * kv;
+    int64_t b0 = 0;
+    int aI = 0;
+    if (live) {
+      const uint64_t key = inv_key[e];
+      const int64_t g = (int64_t)(key >> 8);
+      aI = (int)(key & 255);
+      b0 = gp_ptr[g];
+      const int n = (int)(gp_ptr[g + 1] - b0);
+      const double w = wdet[g];
+      const double c = w * E[gp_cell[g]];
+      const double lc = c * lam, mc = c * mu;
+      const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
+#pragma unroll 2
+      for (int b = ql; b < n; b += 16) {
+        const int32_t J = gp_nbr[b0 + b];
+        const int r = J - lo_I;
+        const uint2 bw = bm[r >> 5];
+        const int pos = (int)bw.y + __popc(bw.x & ((1u << (r & 31)) - 1u));
+        const double* Mb = Mrow + 9 * pos;
+        const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
+        const double tr = Mb[0] + Mb[4] + Mb[8];
+        for (int ga = 0; ga < 3; ++ga) {
+          const double s1 = Mb[3 * ga] * pb[0] + Mb[3 * ga + 1] * pb[1] + Mb[3 * ga + 2] * pb[2];
+          const double s2 = Mb[ga] * pb[0] + Mb[3 + ga] * pb[1] + Mb[6 + ga] * pb[2];
+          v[ga] += lc * s1 + mc * s2 + mc * tr * pb[ga];
         }
-      v[3] += 0.5 * w * kk;
+        const double dot = pI[0] * pb[0] + pI[1] * pb[1] + pI[2] * pb[2];
+        double kk = 0.0;
+        for (int al = 0; al < 3; ++al)
+          for (int be = 0; be < 3; ++be) {
+            const double kv = lam * pI[al] * pb[be] + mu * pI[be] * pb[al] + (al == be ? mu * dot : 0.0);
+            kk += Mb[3 * al + be] * kv;
+          }
+        v[3] += 0.5 * w * kk;
+      }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
+    for (int o = 8; o > 0; o >>= 1)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 64);
-    if (lane == 0) {
+      for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 16);
+    if (live && ql == 0) {
       const int64_t slot = b0 + aI;
       pbar[3 * slot] = v[0];
       pbar[3 * slot + 1] = v[1];
@@ -149,9 +161,12 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   double* gm = lamv + 3 * N;      // [3][N] gamma_k
   double* y = gm + 3 * N;         // [3][N] forward values by position
   double* xs = y + 3 * N;         // [n][3] support coordinates
-  int* S = (int*)(xs + 3 * n);    // [n]
+  int64_t* rwbS = (int64_t*)(xs + 3 * n);  // [n] rank-word offset of each support node's row
+  int64_t* rbpS = rwbS + n;                // [n] pattern start of each support node's row
+  int* S = (int*)(rbpS + n);      // [n]
   int* rowat = S + n;             // [N] original row at each position
   int* posf = rowat + N;          // [N] final position of each original row
+  int* rloS = posf + N;           // [n] window start of each support node's row
   const int64_t o = b0 + 4 * g;
   const double* Lm = lu + lu_off[g];      // multipliers [k][original row]
   const double* U = Lm + (int64_t)N * N;  // U column-major by position
@@ -159,6 +174,9 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   for (int i = tid; i < n; i += kT) {
     const int32_t sidx = gp_nbr[b0 + i];
     S[i] = sidx;
+    rloS[i] = row_lo[sidx];
+    rwbS[i] = rbm_off[sidx];
+    rbpS[i] = blk_ptr[sidx];
     for (int k = 0; k < 3; ++k) xs[3 * i + k] = X[3 * (int64_t)sidx + k];
   }
   for (int i = tid; i < N; i += kT) rowat[i] = piv[o + i];
@@ -173,36 +191,74 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   __syncthreads();
   const int my_posf = own ? posf[tid] : -1;
   // forward substitution on original rows
-  double lnext = (own && N > 0) ? Lm[tid] : 0.0;
-  for (int k = 0; k < N; ++k) {
-    const double lk = lnext;
-    if (own && k + 1 < N) lnext = Lm[(int64_t)(k + 1) * N + tid];
-    if (own && my_posf == k)
-      for (int j = 0; j < 3; ++j) y[j * N + k] = b[j];
-    __syncthreads();
-    if (own && my_posf > k)
-      for (int j = 0; j < 3; ++j) b[j] = __builtin_fma(-lk, y[j * N + k], b[j]);
+  // Factor entries are read PF steps ahead into registers (coalesced over the
+  // threads; addresses clamped into the point's factors so the loads need no
+  // branch), so each step's barrier does not wait on memory.
+  constexpr int PF = 8;
+  const int trow = own ? tid : 0;
+  double fcur[PF], fnxt[PF];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) fcur[j] = Lm[(int64_t)(j < N ? j : N - 1) * N + trow];
+  for (int k0 = 0; k0 < N; k0 += PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int kk = k0 + PF + j;
+      fnxt[j] = Lm[(int64_t)(kk < N ? kk : N - 1) * N + trow];
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int k = k0 + j;
+      if (k < N) {  // uniform
+        if (own && my_posf == k)
+          for (int c = 0; c < 3; ++c) y[c * N + k] = b[c];
+        __syncthreads();
+        if (own && my_posf > k)
+          for (int c = 0; c < 3; ++c) b[c] = __builtin_fma(-fcur[j], y[c * N + k], b[c]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) fcur[j] = fnxt[j];
   }
   __syncthreads();
-  // back substitution by position: thread p holds y_p
+  // back substitution by position: thread p holds y_p; u_{p,k} read PF steps ahead
   double yp[3] = {0.0, 0.0, 0.0};
   if (own)
     for (int j = 0; j < 3; ++j) yp[j] = y[j * N + tid];
-  double unext = own ? U[(int64_t)(N - 1) * N + tid] : 0.0;
-  for (int k = N - 1; k >= 0; --k) {
-    const double uk = unext;  // u_{tid,k}
-    if (own && k > 0) unext = U[(int64_t)(k - 1) * N + tid];
-    if (tid == k)
-      for (int j = 0; j < 3; ++j) {
-        yp[j] = yp[j] / uk;
-        lamv[j * N + k] = yp[j];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    const int kk = N - 1 - j;
+    fcur[j] = U[(int64_t)(kk >= 0 ? kk : 0) * N + trow];
+  }
+  for (int k0 = N - 1; k0 >= 0; k0 -= PF) {
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int kk = k0 - PF - j;
+      fnxt[j] = U[(int64_t)(kk >= 0 ? kk : 0) * N + trow];
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const int k = k0 - j;
+      if (k >= 0) {  // uniform
+        const double uk = fcur[j];  // u_{tid,k}
+        if (tid == k)
+          for (int c = 0; c < 3; ++c) {
+            yp[c] = yp[c] / uk;
+            lamv[c * N + k] = yp[c];
+          }
+        __syncthreads();
+        if (tid < k)
+          for (int c = 0; c < 3; ++c) yp[c] = __builtin_fma(-uk, lamv[c * N + k], yp[c]);
       }
-    __syncthreads();
-    if (tid < k)
-      for (int j = 0; j < 3; ++j) yp[j] = __builtin_fma(-uk, lamv[j * N + k], yp[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < PF; ++j) fcur[j] = fnxt[j];
   }
   __syncthreads();
   // chain rule: four threads per support node a, partial sums over b = sub mod 4
+  // in ascending b.  R_ab is read as entry (S[b], S[a]) of row S[b] of the pair
+  // table (symmetric bit for bit), four b at a time with the loads first: one
+  // load instruction touches four rows (one per sub) at the columns of sixteen
+  // consecutive support nodes.
   for (int a0 = 0; a0 < n; a0 += kT / 4) {
     const int a = a0 + tid / 4, sub = tid & 3;
     double acc[3] = {0.0, 0.0, 0.0};
@@ -211,21 +267,35 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
       const double la[3] = {lamv[a], lamv[N + a], lamv[2 * N + a]};
       const double ga[3] = {gm[a], gm[N + a], gm[2 * N + a]};
       const int32_t Ia = S[a];
-      const int lo_a = row_lo[Ia];
-      const int64_t wb_a = rbm_off[Ia], bp_a = blk_ptr[Ia];
-      for (int bb = sub; bb < n; bb += 4) {
-        if (bb == a) continue;
-        const double gsum = -(la[0] * gm[bb] + la[1] * gm[N + bb] + la[2] * gm[2 * N + bb] + lamv[bb] * ga[0] +
-                              lamv[N + bb] * ga[1] + lamv[2 * N + bb] * ga[2]);
-        const double dx = xa[0] - xs[3 * bb], dy = xa[1] - xs[3 * bb + 1], dz = xa[2] - xs[3 * bb + 2];
-        const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
-        const int r = S[bb] - lo_a;
-        const uint2 wv = rbm[wb_a + (r >> 5)];
-        const double Rab = R[bp_a + (int64_t)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u))];
-        const double f = gsum * (q * Rab / t) * 2.0;
-        acc[0] += f * dx;
-        acc[1] += f * dy;
-        acc[2] += f * dz;
+      for (int bb0 = sub; bb0 < n; bb0 += 16) {
+        uint2 wv[4];
+        int rr[4];
+        double Rv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int bb = bb0 + 4 * j, bs = bb < n ? bb : sub;
+          rr[j] = Ia - rloS[bs];
+          wv[j] = rbm[rwbS[bs] + (rr[j] >> 5)];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int bb = bb0 + 4 * j, bs = bb < n ? bb : sub;
+          Rv[j] = R[rbpS[bs] + (int64_t)wv[j].y + __popc(wv[j].x & ((1u << (rr[j] & 31)) - 1u))];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int bb = bb0 + 4 * j;
+          if (bb < n && bb != a) {
+            const double gsum = -(la[0] * gm[bb] + la[1] * gm[N + bb] + la[2] * gm[2 * N + bb] + lamv[bb] * ga[0] +
+                                  lamv[N + bb] * ga[1] + lamv[2 * N + bb] * ga[2]);
+            const double dx = xa[0] - xs[3 * bb], dy = xa[1] - xs[3 * bb + 1], dz = xa[2] - xs[3 * bb + 2];
+            const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
+            const double f = gsum * (q * Rv[j] / t) * 2.0;
+            acc[0] += f * dx;
+            acc[1] += f * dy;
+            acc[2] += f * dz;
+          }
+        }
       }
     }
     // fixed-order reduction over the four threads of each node
@@ -331,7 +401,7 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   phase_begin(p, RPIM_PHASE_BWD_GP, s);
   for (const Bucket& b : p->buckets) {
     const int N = b.nmax;
-    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int) * (size_t)(3 * N);
+    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(4 * N);
     hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(kT), lds, s, (const int32_t*)p->gp_order, b.begin,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,

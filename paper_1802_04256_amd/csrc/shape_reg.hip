@@ -17,9 +17,11 @@
 // Back substitution then runs by position from the U rows in LDS, k
 // descending: x_k = b_k / u_kk, b_r = fma(-u_rk, x_k, b_r) for r < k.
 //
-// Every register index is static: element 0 is always the pivot column and
-// the shifted update walks the window in 4-column chunks, skipping chunks
-// past the row's end under uniform branches.  Code size is O(NMAX).
+// Every register index is static: element 0 is always the pivot column.  The
+// publish and the shifted update walk the window in blocks of BLK columns and
+// skip blocks past the row's end under uniform branches; the update requests
+// block c+1 of the pivot row from LDS before it issues the fmas of block c.
+// Code size is O(NMAX).
 #include <cfloat>
 #include <climits>
 
@@ -80,12 +82,63 @@ __device__ __forceinline__ double wave_max_nonneg(double x) {
   return b;
 }
 
+// Candidate publish: dst[j] = a[j + 1] for the blocks in use.
+template <int NBLK, int BLK, int WC>
+__device__ __forceinline__ void publish_window(const double (&a)[WC], double* dst, int len) {
+#pragma unroll
+  for (int c = 0; c < NBLK; ++c) {
+    if (BLK * c < len) {
+#pragma unroll
+      for (int e = 0; e < BLK; e += 2) {
+        const int j = BLK * c + e;
+        if (j + 2 < WC) *reinterpret_cast<double2*>(dst + j) = make_double2(a[j + 1], a[j + 2]);
+        else if (j + 1 < WC) dst[j] = a[j + 1];
+      }
+    }
+  }
+}
+
+// Update-and-shift, a[j] <- fma(-l, u[j], a[j + 1]) for the blocks in use; the
+// window's last element becomes zero.  Each block requests the next block of
+// the pivot row from LDS before it issues its own fmas (the pivot-row buffer
+// is padded to whole blocks, so the request past the row's end stays inside
+// it).
+template <int NBLK, int BLK, int WC>
+__device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const double* u, int len) {
+  double ub[2][BLK];
+#pragma unroll
+  for (int e = 0; e < BLK; e += 2) {
+    const double2 v = *reinterpret_cast<const double2*>(u + e);
+    ub[0][e] = v.x;
+    ub[0][e + 1] = v.y;
+  }
+#pragma unroll
+  for (int c = 0; c < NBLK; ++c) {
+    if (BLK * c < len) {
+      if (c + 1 < NBLK) {
+#pragma unroll
+        for (int e = 0; e < BLK; e += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(u + BLK * (c + 1) + e);
+          ub[(c + 1) & 1][e] = v.x;
+          ub[(c + 1) & 1][e + 1] = v.y;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < BLK; ++e) {
+        const int j = BLK * c + e;
+        if (j + 1 < WC) a[j] = __builtin_fma(nl, ub[c & 1][e], a[j + 1]);
+        else if (j < WC) a[j] = 0.0;
+      }
+    }
+  }
+}
+
 template <int NMAX>
 constexpr int u_size() {
   return NMAX * (NMAX + 7) / 2 + 8;  // sum over positions k < N <= NMAX of (NMAX + 3 - k)
 }
 
-template <int NMAX, int WAVES>
+template <int NMAX, int WAVES, int BLK>
 __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr, const int32_t* gp_nbr,
     const int64_t* blk_ptr, const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* R,
@@ -93,12 +146,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
   constexpr int T = 64 * WAVES;
   constexpr int WC = NMAX + 4;   // window: matrix columns + 3 right-hand sides + 1 zero
-  constexpr int NCH = WC / 4;    // 4-column chunks
-  constexpr int BLK = NMAX <= 72 ? 32 : (NMAX <= 96 ? 16 : 8);  // update block (register budget)
   constexpr int NBLK = (WC + BLK - 1) / BLK;
   constexpr int US = u_size<NMAX>();
   constexpr int LDSD = US;
-  static_assert(T >= NMAX && NMAX % 8 == 0, "shape");
+  static_assert(T >= NMAX && NMAX % 8 == 0 && BLK % 2 == 0, "shape");
   __shared__ __align__(16) double lds[LDSD];            // the U rows
   __shared__ __align__(16) double prow[2][WAVES][NBLK * BLK];  // candidate windows shifted by one: prow[j] = w[j+1]
   __shared__ double cval[2][WAVES];
@@ -141,29 +192,47 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   }
   __syncthreads();
 
-  // ---- build: thread r fills its own row in registers ---------------------------
+  // ---- build: thread t fills row t of [G | rhs] in registers ---------------------
   // Columns 0..N-1 of G (zero padding up to NMAX), then the three right-hand
-  // sides at NMAX..NMAX+2.  Every column index is static; the radial-basis
-  // entries of a row are n independent (rank word, value) load pairs.
+  // sides at NMAX..NMAX+2.  The radial-basis block is symmetric bit for bit
+  // (the pair table evaluates each ordered pair from x_I - x_J, and squares
+  // do not see the sign), so lane t reads entry (S[c], S[t]) from row S[c] of
+  // the pair table: the row's window, rank words and start are uniform over
+  // the workgroup, and the lanes' loads fall into a few adjacent words and
+  // values of that one row.  The loads run branch-free in batches of CB
+  // columns (past-the-end columns look up column 0 and are overwritten), so
+  // each batch's rank words are all in flight before its values are needed.
   double a[WC];
   if (t < n) {
-    const int lo_r = rlo[t];
-    const int64_t wb_r = rwb[t], bp_r = rbp[t];
+    constexpr int CB = 8;
+    static_assert(NMAX % CB == 0, "batch");
+    const int my_id = S[t];
+#pragma unroll
+    for (int c0 = 0; c0 < NMAX; c0 += CB) {
+      uint2 wd[CB];
+      int rl[CB];
+#pragma unroll
+      for (int e = 0; e < CB; ++e) {
+        const int cs = c0 + e < n ? c0 + e : 0;
+        rl[e] = my_id - rlo[cs];
+        wd[e] = rbm[rwb[cs] + (rl[e] >> 5)];
+      }
+#pragma unroll
+      for (int e = 0; e < CB; ++e) {
+        const int cs = c0 + e < n ? c0 + e : 0;
+        a[c0 + e] = R[rbp[cs] + (int64_t)wd[e].y + __popc(wd[e].x & ((1u << (rl[e] & 31)) - 1u))];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep batches apart: bounded registers in flight
+    }
+    // columns n..N-1: [1, x_t - x_g]; zero padding after them
     const double xr0 = xs[3 * t], xr1 = xs[3 * t + 1], xr2 = xs[3 * t + 2];
+    const double d0 = xr0 - xg[0], d1 = xr1 - xg[1], d2 = xr2 - xg[2];
 #pragma unroll
     for (int c = 0; c < NMAX; ++c) {
-      double v = 0.0;
-      if (c < n) {
-        const int rel = S[c] - lo_r;
-        const uint2 wd = rbm[wb_r + (rel >> 5)];
-        v = R[bp_r + (int64_t)wd.y + __popc(wd.x & ((1u << (rel & 31)) - 1u))];
-      } else if (c == n) {
-        v = 1.0;
-      } else if (c < N) {
-        const int k = c - n - 1;
-        v = (k == 0 ? xr0 : (k == 1 ? xr1 : xr2)) - xg[k];
+      if (c >= n) {  // uniform
+        const int kk = c - n;
+        a[c] = kk == 0 ? 1.0 : (kk == 1 ? d0 : (kk == 2 ? d1 : (kk == 3 ? d2 : 0.0)));
       }
-      a[c] = v;
     }
     const double cf = coefs[t];
     a[NMAX] = cf * (xg[0] - xr0);
@@ -212,14 +281,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     unsigned key;
     wave_argmax(fabs(a[0]), active, ((unsigned)pos << 8) | (unsigned)t, &v, &key);
     if ((key & 255u) == (unsigned)t) {  // this wave's candidate publishes its window
-#pragma unroll
-      for (int c = 0; c < NCH; ++c) {
-        if (4 * c < len) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (4 * c + e + 1 < WC) prow[buf][w][4 * c + e] = a[4 * c + e + 1];
-        }
-      }
+      publish_window<NBLK, BLK, WC>(a, prow[buf][w], len);
       cpiv[buf][w] = a[0];
     }
     if (lane == 0) {
@@ -234,47 +296,28 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     for (int i = 1; i < WAVES; ++i) {
       const double v2 = cval[buf][i];
       const unsigned k2 = ckey[buf][i];
-      if (v2 > best || (v2 == best && k2 < bkey)) { best = v2; bkey = k2; bw = i; }
+      const bool take = v2 > best || (v2 == best && k2 < bkey);
+      best = take ? v2 : best;
+      bkey = take ? k2 : bkey;
+      bw = take ? i : bw;
     }
     if (!(best > tiny)) {
       if (t == 0) flag_error(st, kFlagSingular, g);
       return;  // uniform: every thread saw the same best
     }
     const int prow_id = (int)(bkey & 255u), ppos = (int)(bkey >> 8);
-    const double* u = prow[buf][bw];  // u[j] = pivot column k+1+j
-    const double ukk = cpiv[buf][bw];
-    // keep the pivot window as U row k
-    if (t == 0) lds[uoff] = ukk;
-    for (int i = t; i < len - 1; i += T) lds[uoff + 1 + i] = u[i];
     if (t == 0) rowat[k] = prow_id;
     if (t == prow_id) pos = k;
     else if (pos == k) pos = ppos;
     if (real && pos > k) {
-      const double l = a[0] / ukk;
+      const double l = a[0] / cpiv[buf][bw];
       if (keep) Lkeep[(int64_t)k * N + t] = l;
-      // update and shift: element j takes column k+1+j.  Blocks of BLK columns:
-      // all of a block's pivot-row loads are in flight before its first fma.
-#pragma unroll
-      for (int c = 0; c < NBLK; ++c) {
-        if (BLK * c < len) {
-          double uu[BLK];
-#pragma unroll
-          for (int e = 0; e < BLK; e += 2) {
-            if (BLK * c + e < WC) {
-              const double2 v2 = *reinterpret_cast<const double2*>(u + BLK * c + e);
-              uu[e] = v2.x;
-              uu[e + 1] = v2.y;
-            }
-          }
-#pragma unroll
-          for (int e = 0; e < BLK; ++e) {
-            const int j = BLK * c + e;
-            if (j + 1 < WC) a[j] = __builtin_fma(-l, uu[e], a[j + 1]);
-            else if (j < WC) a[j] = 0.0;
-          }
-        }
-      }
+      shift_update<NBLK, BLK, WC>(a, -l, prow[buf][bw], len);  // prow[j] = pivot column k+1+j
     }
+    // keep the pivot's window as U row k, one element per thread; the buffer is
+    // not written again before the next step's barrier
+    if (t == 0) lds[uoff] = cpiv[buf][bw];
+    for (int i = t; i < len - 1; i += T) lds[uoff + 1 + i] = prow[buf][bw][i];
     uoff += len;
   }
   __syncthreads();
@@ -318,9 +361,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   if (keep) {
     // U by position, column-major (U[c*N + p] = u_pc), after the multipliers
     double* U = Lkeep + (int64_t)N * N;
-    for (int k = 0; k < N; ++k) {
-      const int off = k * (NMAX + 3) - (k * (k - 1)) / 2;
-      for (int j = t; j < N - k; j += T) U[(int64_t)(k + j) * N + k] = lds[off + j];
+    if (t < N) {
+      const int off = t * (NMAX + 3) - (t * (t - 1)) / 2;
+      for (int c = 0; c < N; ++c)
+        if (t <= c) U[(int64_t)c * N + t] = lds[off + (c - t)];
     }
     const int64_t o = b0 + 4 * g;
     for (int i = t; i < N; i += T) piv_out[o + i] = rowat[i];
@@ -331,9 +375,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   }
 }
 
-template <int NMAX, int WAVES>
+template <int NMAX, int WAVES, int BLK>
 rpim_status launch_one(rpim_plan* p, const Bucket& bk, const double* X, double C2, int keep, hipStream_t s) {
-  hipLaunchKernelGGL((k_shape_win<NMAX, WAVES>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
+  hipLaunchKernelGGL((k_shape_win<NMAX, WAVES, BLK>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
                      (const int32_t*)p->gp_order, bk.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
                      (const int64_t*)p->blk_ptr, (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off,
                      (const uint2*)p->rbm, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, p->dphi,
@@ -349,18 +393,18 @@ int shape_reg_max() { return 104; }
 
 rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, hipStream_t s) {
   switch (b.nmax) {
-    case 8: case 16: return launch_one<16, 1>(p, b, X, C2, keep, s);
-    case 24: return launch_one<24, 1>(p, b, X, C2, keep, s);
-    case 32: return launch_one<32, 1>(p, b, X, C2, keep, s);
-    case 40: return launch_one<40, 1>(p, b, X, C2, keep, s);
-    case 48: return launch_one<48, 1>(p, b, X, C2, keep, s);
-    case 56: return launch_one<56, 1>(p, b, X, C2, keep, s);
-    case 64: return launch_one<64, 1>(p, b, X, C2, keep, s);
-    case 72: return launch_one<72, 2>(p, b, X, C2, keep, s);
-    case 80: return launch_one<80, 2>(p, b, X, C2, keep, s);
-    case 88: return launch_one<88, 2>(p, b, X, C2, keep, s);
-    case 96: return launch_one<96, 2>(p, b, X, C2, keep, s);
-    case 104: return launch_one<104, 2>(p, b, X, C2, keep, s);
+    case 8: case 16: return launch_one<16, 1, 16>(p, b, X, C2, keep, s);
+    case 24: return launch_one<24, 1, 16>(p, b, X, C2, keep, s);
+    case 32: return launch_one<32, 1, 16>(p, b, X, C2, keep, s);
+    case 40: return launch_one<40, 1, 16>(p, b, X, C2, keep, s);
+    case 48: return launch_one<48, 1, 16>(p, b, X, C2, keep, s);
+    case 56: return launch_one<56, 1, 16>(p, b, X, C2, keep, s);
+    case 64: return launch_one<64, 1, 16>(p, b, X, C2, keep, s);
+    case 72: return launch_one<72, 2, 8>(p, b, X, C2, keep, s);
+    case 80: return launch_one<80, 2, 8>(p, b, X, C2, keep, s);
+    case 88: return launch_one<88, 2, 8>(p, b, X, C2, keep, s);
+    case 96: return launch_one<96, 2, 8>(p, b, X, C2, keep, s);
+    case 104: return launch_one<104, 2, 8>(p, b, X, C2, keep, s);
     default: return RPIM_E_RANGE;
   }
 }
