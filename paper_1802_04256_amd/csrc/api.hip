@@ -235,6 +235,7 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
   hipStream_t s = (hipStream_t)stream;
   rpim_status st;
   if ((st = ensure(&p->R, &p->cap_R, p->nblk)) || (st = ensure(&p->dphi, &p->cap_dphi, 3 * p->sum_n))) return st;
+  if (precision == RPIM_MIXED && (st = ensure(&p->dphi32, &p->cap_dphi32, 3 * p->sum_n))) return st;
   if (keep_factors) {
     if ((st = ensure(&p->lu, &p->cap_lu, p->lu_doubles)) || (st = ensure(&p->piv, &p->cap_piv, p->sum_n + 4 * p->G)) ||
         (st = ensure(&p->gam, &p->cap_gam, 3 * (p->sum_n + 4 * p->G))))
@@ -245,7 +246,9 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
   if ((st = launch_pair_table(p, node_xyz, s)) != RPIM_OK) return st;
   phase_end(p, RPIM_PHASE_PAIRS, s);
   phase_begin(p, RPIM_PHASE_SHAPE, s);
-  if ((st = launch_shape(p, node_xyz, keep_factors ? 1 : 0, s)) != RPIM_OK) return st;
+  if ((st = launch_shape(p, node_xyz, keep_factors ? 1 : 0, precision == RPIM_MIXED ? p->dphi32 : nullptr, s)) !=
+      RPIM_OK)
+    return st;
   phase_end(p, RPIM_PHASE_SHAPE, s);
   phase_begin(p, RPIM_PHASE_GATHER, s);
   if ((st = launch_rowgather(p, cell_E, nu, precision, K_vals, s)) != RPIM_OK) return st;

@@ -13,7 +13,10 @@
 //         dot = fma(pI2,pJ2, fma(pI1,pJ1, pI0 pJ0)).
 //   K   : +0 + e_g1 + e_g2 + ... over contributing points in ascending g.
 #include <cfloat>
+#include <climits>
 #include <cstdlib>
+
+#include <type_traits>
 
 #include "dd_pow.h"
 #include "rpim_internal.h"
@@ -88,7 +91,8 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
                                                     const int64_t* blk_ptr, const int32_t* row_lo,
                                                     const int64_t* rbm_off, const uint2* rbm, const double* R,
                                                     const double* X, const double* gp_xyz, double C2, double q,
-                                                    int ld, double* dphi, int keep, const int64_t* lu_off,
+                                                    int ld, double* dphi, float* dphi32, int keep,
+                                                    const int64_t* lu_off,
                                                     double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
   extern __shared__ double smem[];
   __shared__ double red_v[kThreads / 64];
@@ -199,6 +203,7 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
   for (int idx = tid; idx < 3 * n; idx += kThreads) {
     const int a = idx / 3, k = idx - 3 * a;
     dphi[3 * (b0 + a) + k] = A[a * ld + N + k];
+    if (dphi32) dphi32[3 * (b0 + a) + k] = (float)A[a * ld + N + k];
   }
   if (keep) {
     double* L = lu + lu_off[g];  // multipliers by (step, original row), then U rows by position
@@ -218,43 +223,65 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 }
 
 // ---- row gather: one workgroup per node row I --------------------------------
-// acc[pos][9] over the row's column blocks.  Wave w owns the accumulators of
-// displacement component alpha = w (three waves), so the waves never touch the
-// same slot; each wave walks the row's Gauss points in ascending g and, since
-// a wave's LDS accesses execute in program order, every slot receives its
-// contributions in ascending g without any barrier.
-constexpr int kGatherThreads = 192;
+// acc[pos][9] over the row's column blocks (pos = rank of J in row I).  The
+// row's columns are cut into kGatherWaves ranges of node ids and wave w owns
+// the slots of its range, so no slot is touched by two waves.  Each wave walks
+// the row's Gauss points in ascending g; since supports are sorted, the part
+// of a point's support inside the wave's range is a contiguous run, found with
+// two ballots, and its entries go one per lane, each lane adding all nine
+// entries of its 3x3 block.  A wave's LDS accesses execute in program order,
+// so every slot receives its contributions in ascending g without barriers.
+constexpr int kGatherWaves = 2;
+constexpr int kGatherThreads = 64 * kGatherWaves;
 
 template <bool kMixed>
-__global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* row_lo,
+__global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
+                                                              const int32_t* row_lo,
                                                               const int64_t* rbm_off, const uint2* rbm,
                                                               const int64_t* inv_ptr, const uint64_t* inv_key,
                                                               const int64_t* gp_ptr, const int32_t* gp_nbr,
-                                                              const double* dphi, const double* wdet,
+                                                              const void* dphi_any, const double* wdet,
                                                               const int32_t* gp_cell, const double* E, double lam,
                                                               double mu, void* Kout) {
   extern __shared__ double smem[];
+  // gradients: FP64, or rounded to float by the solver for the mixed path
+  using T = typename std::conditional<kMixed, float, double>::type;
+  const T* dphi = static_cast<const T*>(dphi_any);
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
   double* acc = smem;                 // [L][9] FP64, or [L][9] float2 (sum, compensation)
   uint2* bm = (uint2*)(acc + 9 * L);  // row I's rank bitmap
   const int tid = threadIdx.x;
-  const int al = tid >> 6, lane = tid & 63;
+  const int w = tid >> 6, lane = tid & 63;
   const int lo_I = row_lo[I];
   const int64_t wb = rbm_off[I];
   const int nw = (int)(rbm_off[I + 1] - wb);
   for (int i = tid; i < nw; i += kGatherThreads) bm[i] = rbm[wb + i];
   for (int i = tid; i < 9 * L; i += kGatherThreads) acc[i] = 0.0;
+  // this wave's columns: node ids in [thr_lo, thr_hi)
+  const int32_t thr_lo = w == 0 ? INT_MIN : blk_col[rb + (int64_t)w * L / kGatherWaves];
+  const int32_t thr_hi = w + 1 == kGatherWaves ? INT_MAX : blk_col[rb + (int64_t)(w + 1) * L / kGatherWaves];
   __syncthreads();
-  // Software pipeline over the row's Gauss points: point metadata (scalar) is
-  // fetched three points ahead, the per-lane support entries two points
-  // ahead, so the dependent global loads overlap the accumulation.  Loads past
-  // the row's last point re-read the last point (no branch around a load).
+
+  // Software pipeline over the row's Gauss points: point metadata (scalar)
+  // three points ahead, the support ids that locate the wave's run two points
+  // ahead, the run's entries one point ahead.  Loads past the row's last point
+  // re-read the last point, loads past a support's end re-read its last entry
+  // (no branch around a load).
   struct Meta {
     int64_t b0;
     int n, aI;
     double lc, mc;
+  };
+  struct Split {
+    int32_t J0, J1;  // support ids at b = lane and b = lane + 64
+  };
+  struct Run {
+    int lo, hi;      // the wave's part of the support: b in [lo, hi)
+    int32_t J;       // entry b = lo + lane
+    T p[3];
+    T pI[3];
   };
   const int64_t e_beg = inv_ptr[I], e_end = inv_ptr[I + 1];
   auto meta = [&](int64_t e) {
@@ -269,92 +296,101 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
     m.mc = c * mu;
     return m;
   };
-  struct Lanes {
-    int32_t J[2];
-    double pJ[2][3];
-    double pI[3];
+  auto split = [&](const Meta& m) {
+    Split sp;
+    const int b1 = lane + 64 < m.n ? lane + 64 : m.n - 1;
+    sp.J0 = gp_nbr[m.b0 + (lane < m.n ? lane : m.n - 1)];
+    sp.J1 = gp_nbr[m.b0 + b1];
+    return sp;
   };
-  auto lanes = [&](const Meta& m) {
-    Lanes l;
-    for (int k = 0; k < 3; ++k) l.pI[k] = dphi[3 * (m.b0 + m.aI) + k];
+  auto run = [&](const Meta& m, const Split& sp) {
+    Run r;
+    // supports are sorted: the count of ids below a threshold is a position
+    const bool v0 = lane < m.n, v1 = lane + 64 < m.n;
+    r.lo = __popcll(__ballot(v0 && sp.J0 < thr_lo)) + __popcll(__ballot(v1 && sp.J1 < thr_lo));
+    r.hi = __popcll(__ballot(v0 && sp.J0 < thr_hi)) + __popcll(__ballot(v1 && sp.J1 < thr_hi));
+    const int b = r.lo + lane;
+    const int bc = b < m.n ? b : m.n - 1;
+    r.J = gp_nbr[m.b0 + bc];
+    for (int k = 0; k < 3; ++k) r.p[k] = dphi[3 * (m.b0 + bc) + k];
+    for (int k = 0; k < 3; ++k) r.pI[k] = dphi[3 * (m.b0 + m.aI) + k];
+    return r;
+  };
+  // all nine entries of block (I, J) of one point, added to its slot
+  auto accum = [&](int32_t J, const T (&pJ)[3], const T (&pI)[3], double lc, double mc) {
+    const int r = J - lo_I;
+    const uint2 wv = bm[r >> 5];
+    const int pos = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
+    if constexpr (!kMixed) {
+      const double dot = __builtin_fma(pI[2], pJ[2], __builtin_fma(pI[1], pJ[1], pI[0] * pJ[0]));
+      double m[3][3];
 #pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int b = lane + 64 * s2;
-      const int bc = b < m.n ? b : m.n - 1;  // lanes past the support re-read its last entry
-      const int32_t J = gp_nbr[m.b0 + bc];
-      l.J[s2] = b < m.n ? J : -1;
-      for (int k = 0; k < 3; ++k) l.pJ[s2][k] = dphi[3 * (m.b0 + bc) + k];
-    }
-    return l;
-  };
-  const int64_t e_last = e_end - 1;
-  auto clampe = [&](int64_t e) { return e < e_last ? e : e_last; };
-  Meta m_cur = {}, m_nxt = {}, m_n2 = {};
-  Lanes l_cur = {}, l_nxt = {};
-  if (e_beg < e_end) {
-    m_cur = meta(e_beg);
-    m_nxt = meta(clampe(e_beg + 1));
-    l_cur = lanes(m_cur);
-    m_n2 = meta(clampe(e_beg + 2));
-    l_nxt = lanes(m_nxt);
-  }
-  for (int64_t e = e_beg; e < e_end; ++e) {
-    const Meta m_n3 = meta(clampe(e + 3));
-    const Lanes l_n2 = lanes(m_n2);
-    const double lc = m_cur.lc, mc = m_cur.mc;
-    const double pI0 = l_cur.pI[0], pI1 = l_cur.pI[1], pI2 = l_cur.pI[2];
-    // this wave's component alpha of phi_I (no dynamic register indexing)
-    const double pIa = al == 0 ? pI0 : (al == 1 ? pI1 : pI2);
-    auto accum = [&](int32_t J, double pJ0, double pJ1, double pJ2) {
-      const int r = J - lo_I;
-      const uint2 wv = bm[r >> 5];
-      const int pos = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
-      const double pJa = al == 0 ? pJ0 : (al == 1 ? pJ1 : pJ2);
-      const double pJb[3] = {pJ0, pJ1, pJ2};
-      const double pIb[3] = {pI0, pI1, pI2};
-      if (!kMixed) {
-        const double dot = __builtin_fma(pI2, pJ2, __builtin_fma(pI1, pJ1, pI0 * pJ0));
-        double* a = acc + 9 * pos + 3 * al;
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) m[al][be] = pI[al] * pJ[be];
+      double* a = acc + 9 * pos;
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
 #pragma unroll
         for (int be = 0; be < 3; ++be) {
-          const double m1 = pIa * pJb[be];
-          double m2 = pIb[be] * pJa;
+          double m2 = m[be][al];  // phi_I,beta * phi_J,alpha
           if (al == be) m2 = m2 + dot;
-          a[be] = a[be] + __builtin_fma(lc, m1, mc * m2);
+          a[3 * al + be] = a[3 * al + be] + __builtin_fma(lc, m[al][be], mc * m2);
         }
-      } else {
-        const float fIa = (float)pIa, fJa = (float)pJa;
-        const float fI[3] = {(float)pI0, (float)pI1, (float)pI2}, fJ[3] = {(float)pJ0, (float)pJ1, (float)pJ2};
-        const float flc = (float)lc, fmc = (float)mc;
-        const float dot = __builtin_fmaf(fI[2], fJ[2], __builtin_fmaf(fI[1], fJ[1], fI[0] * fJ[0]));
-        float2* a = reinterpret_cast<float2*>(acc) + 9 * pos + 3 * al;
+    } else {
+      const float flc = (float)lc, fmc = (float)mc;
+      const float dot = __builtin_fmaf(pI[2], pJ[2], __builtin_fmaf(pI[1], pJ[1], pI[0] * pJ[0]));
+      float m[3][3];
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) m[al][be] = pI[al] * pJ[be];
+      float2* a = reinterpret_cast<float2*>(acc) + 9 * pos;
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
 #pragma unroll
         for (int be = 0; be < 3; ++be) {
-          const float m1 = fIa * fJ[be];
-          float m2 = fI[be] * fJa;
+          float m2 = m[be][al];
           if (al == be) m2 = m2 + dot;
-          const float ev = __builtin_fmaf(flc, m1, fmc * m2);
-          float2 sc = a[be];
+          const float ev = __builtin_fmaf(flc, m[al][be], fmc * m2);
+          float2 sc = a[3 * al + be];  // Kahan: (sum, compensation)
           const float y = ev - sc.y;
           const float t = sc.x + y;
           sc.y = (t - sc.x) - y;
           sc.x = t;
-          a[be] = sc;
+          a[3 * al + be] = sc;
         }
-      }
-    };
-    if (l_cur.J[0] >= 0) accum(l_cur.J[0], l_cur.pJ[0][0], l_cur.pJ[0][1], l_cur.pJ[0][2]);
-    if (l_cur.J[1] >= 0) accum(l_cur.J[1], l_cur.pJ[1][0], l_cur.pJ[1][1], l_cur.pJ[1][2]);
-    // supports beyond 128 nodes (rare) take a plain loop after the two prefetched slots
-    for (int b = 128 + lane; b < m_cur.n; b += 64) {
+    }
+  };
+  const int64_t e_last = e_end - 1;
+  auto clampe = [&](int64_t e) { return e < e_last ? e : e_last; };
+  Meta m_cur = {}, m_nxt = {}, m_n2 = {};
+  Split s_nxt = {}, s_n2 = {};
+  Run r_cur = {};
+  if (e_beg < e_end) {
+    m_cur = meta(e_beg);
+    m_nxt = meta(clampe(e_beg + 1));
+    const Split s_cur = split(m_cur);
+    m_n2 = meta(clampe(e_beg + 2));
+    s_nxt = split(m_nxt);
+    r_cur = run(m_cur, s_cur);
+  }
+  for (int64_t e = e_beg; e < e_end; ++e) {
+    const Meta m_n3 = meta(clampe(e + 3));
+    s_n2 = split(m_n2);
+    const Run r_nxt = run(m_nxt, s_nxt);
+    if (r_cur.lo + lane < r_cur.hi) accum(r_cur.J, r_cur.p, r_cur.pI, m_cur.lc, m_cur.mc);
+    // runs longer than one wave (supports beyond ~128 nodes) continue in a plain loop
+    for (int b = r_cur.lo + 64 + lane; b < r_cur.hi; b += 64) {
       const int64_t eb = m_cur.b0 + b;
-      accum(gp_nbr[eb], dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]);
+      const T pJ[3] = {dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]};
+      accum(gp_nbr[eb], pJ, r_cur.pI, m_cur.lc, m_cur.mc);
     }
     m_cur = m_nxt;
     m_nxt = m_n2;
     m_n2 = m_n3;
-    l_cur = l_nxt;
-    l_nxt = l_n2;
+    s_nxt = s_n2;
+    r_cur = r_nxt;
   }
   __syncthreads();
   const int64_t base = 9 * rb;
@@ -391,14 +427,14 @@ rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s) {
   return RPIM_OK;
 }
 
-rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s) {
+rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s) {
   const double ac = p->alpha_c * p->d_c;
   const double C2 = ac * ac;
   const char* sel = getenv("RPIM_SHAPE_KERNEL");
   const bool use_reg = !(sel && sel[0] == 'l');  // "lds" selects the shared-memory kernel for every bucket
   for (const Bucket& b : p->buckets) {
     if (use_reg && b.nmax <= shape_reg_max()) {
-      rpim_status st = launch_shape_reg(p, b, X, C2, keep, s);
+      rpim_status st = launch_shape_reg(p, b, X, C2, keep, dphi32, s);
       if (st != RPIM_OK) return st;
       continue;
     }
@@ -411,7 +447,7 @@ rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s)
                        b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
-                       p->dphi, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
+                       p->dphi, dphi32, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
     RPIM_HIP(hipGetLastError());
   }
   return RPIM_OK;
@@ -428,16 +464,18 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   if (precision == RPIM_FP64) {
     if (rpim_status st = lds_limit((const void*)k_rowgather<false>, lds, &g_lds_gather64)) return st;
     hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
+                       (const int32_t*)p->blk_col,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
-                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
+                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const void*)p->dphi,
                        (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
   } else {
     if (rpim_status st = lds_limit((const void*)k_rowgather<true>, lds, &g_lds_gather32)) return st;
     hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
+                       (const int32_t*)p->blk_col,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
-                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
+                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const void*)p->dphi32,
                        (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
   }
   RPIM_HIP(hipGetLastError());

@@ -118,7 +118,7 @@ struct rpim_plan {
   rpim::DevStatus* status = nullptr;
 
   // capacities (elements) of the workspaces above, so a rebuilt pattern can reuse them
-  int64_t cap_R = 0, cap_dphi = 0, cap_lu = 0, cap_piv = 0, cap_gam = 0;
+  int64_t cap_R = 0, cap_dphi = 0, cap_dphi32 = 0, cap_lu = 0, cap_piv = 0, cap_gam = 0;
   int64_t cap_msym = 0, cap_pbar = 0, cap_dEs = 0, cap_dEg = 0, cap_dXs = 0;
 
   // optional per-phase timing with HIP events on the call's stream
@@ -158,11 +158,13 @@ rpim_status expand_pattern(const rpim_plan* p, int64_t* row_ptr, int32_t* col_id
 
 // --- assemble.hip ------------------------------------------------------------
 rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s);
-rpim_status launch_shape(rpim_plan* p, const double* X, int keep, hipStream_t s);
+// dphi32 (may be null): also write the gradients rounded to float, for the mixed-precision gather
+rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s);
 rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K,
                              hipStream_t s);
 int shape_reg_max();
-rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, hipStream_t s);
+rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, float* dphi32,
+                             hipStream_t s);
 rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s);
 
 // --- backward.hip ------------------------------------------------------------

@@ -10,18 +10,26 @@
 //   step k: the pivot is the active row with the largest |a_k| (window
 //           element 0), ties to the smaller position; it takes position k,
 //           the row that held position k takes the pivot's old position.
-//           The pivot publishes its window through LDS; every other active
-//           row computes l = a_k / u_kk and updates-and-shifts its window in
-//           one pass: w_j <- fma(-l, u_{j+1}, w_{j+1}), so column k+1 becomes
-//           element 0.  The pivot row's window (its U row) is kept in LDS.
+//           Each wave's candidate posts (|a_k|, key) in one 16-byte LDS
+//           write; after a barrier every wave picks the winner, and the
+//           winner writes its window once, as U row k, into LDS.  After a
+//           second barrier every other active row computes l = a_k / u_kk and
+//           updates-and-shifts its window in one pass:
+//           w_j <- fma(-l, u_{j+1}, w_{j+1}), so column k+1 becomes element 0.
+//           (With one wave per point both barriers are unnecessary: a wave's
+//           LDS accesses complete in program order.)
 // Back substitution then runs by position from the U rows in LDS, k
 // descending: x_k = b_k / u_kk, b_r = fma(-u_rk, x_k, b_r) for r < k.
 //
 // Every register index is static: element 0 is always the pivot column.  The
-// publish and the shifted update walk the window in blocks of BLK columns and
-// skip blocks past the row's end under uniform branches; the update requests
-// block c+1 of the pivot row from LDS before it issues the fmas of block c.
-// Code size is O(NMAX).
+// winner's write and the update walk the window in blocks of sixteen columns,
+// skipping blocks past the row's end under uniform branches.  The pivot row
+// reaches the other rows one element per lane from LDS and is spread across
+// each row of sixteen lanes by DPP broadcasts.  LDS instructions are the
+// scarce resource of this kernel (each one holds the CU's LDS pipe for about
+// the same time however few lanes it serves, and eight waves share it), so a
+// step issues one candidate write, one winner write per two columns, and per
+// wave one read per sixteen columns.  Code size is O(NMAX).
 #include <cfloat>
 #include <climits>
 
@@ -82,79 +90,105 @@ __device__ __forceinline__ double wave_max_nonneg(double x) {
   return b;
 }
 
-// Candidate publish: dst[j] = a[j + 1] for the blocks in use.
-template <int NBLK, int BLK, int WC>
-__device__ __forceinline__ void publish_window(const double (&a)[WC], double* dst, int len) {
+// The winner's window as U row k: dst[j] = a[j] for the 16-column blocks in
+// use (dst 16-byte aligned; the U storage is padded past its last row).
+template <int NB, int WC>
+__device__ __forceinline__ void write_row(const double (&a)[WC], double* dst, int len) {
 #pragma unroll
-  for (int c = 0; c < NBLK; ++c) {
-    if (BLK * c < len) {
+  for (int c = 0; c < NB; ++c) {
+    if (16 * c < len) {
 #pragma unroll
-      for (int e = 0; e < BLK; e += 2) {
-        const int j = BLK * c + e;
-        if (j + 2 < WC) *reinterpret_cast<double2*>(dst + j) = make_double2(a[j + 1], a[j + 2]);
-        else if (j + 1 < WC) dst[j] = a[j + 1];
+      for (int e = 0; e < 16; e += 2) {
+        const int j = 16 * c + e;
+        if (j + 1 < WC) *reinterpret_cast<double2*>(dst + j) = make_double2(a[j], a[j + 1]);
+        else if (j < WC) dst[j] = a[j];
       }
     }
   }
 }
 
-// Update-and-shift, a[j] <- fma(-l, u[j], a[j + 1]) for the blocks in use; the
-// window's last element becomes zero.  Each block requests the next block of
-// the pivot row from LDS before it issues its own fmas (the pivot-row buffer
-// is padded to whole blocks, so the request past the row's end stays inside
-// it).
-template <int NBLK, int BLK, int WC>
-__device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const double* u, int len) {
-  double ub[2][BLK];
-#pragma unroll
-  for (int e = 0; e < BLK; e += 2) {
-    const double2 v = *reinterpret_cast<const double2*>(u + e);
-    ub[0][e] = v.x;
-    ub[0][e + 1] = v.y;
+// Lane e of each row of sixteen lanes broadcast to the whole row (64-bit DPP
+// row_newbcast).  e must fold to a constant; every lane of the row must be
+// active, since a disabled source lane reads as zero.
+__device__ __forceinline__ double row_bcast(double v, int e) {
+  const long long x = __double_as_longlong(v);
+  long long r;
+  switch (e) {
+    case 0: r = __builtin_amdgcn_update_dpp(x, x, 0x150, 0xF, 0xF, true); break;
+    case 1: r = __builtin_amdgcn_update_dpp(x, x, 0x151, 0xF, 0xF, true); break;
+    case 2: r = __builtin_amdgcn_update_dpp(x, x, 0x152, 0xF, 0xF, true); break;
+    case 3: r = __builtin_amdgcn_update_dpp(x, x, 0x153, 0xF, 0xF, true); break;
+    case 4: r = __builtin_amdgcn_update_dpp(x, x, 0x154, 0xF, 0xF, true); break;
+    case 5: r = __builtin_amdgcn_update_dpp(x, x, 0x155, 0xF, 0xF, true); break;
+    case 6: r = __builtin_amdgcn_update_dpp(x, x, 0x156, 0xF, 0xF, true); break;
+    case 7: r = __builtin_amdgcn_update_dpp(x, x, 0x157, 0xF, 0xF, true); break;
+    case 8: r = __builtin_amdgcn_update_dpp(x, x, 0x158, 0xF, 0xF, true); break;
+    case 9: r = __builtin_amdgcn_update_dpp(x, x, 0x159, 0xF, 0xF, true); break;
+    case 10: r = __builtin_amdgcn_update_dpp(x, x, 0x15A, 0xF, 0xF, true); break;
+    case 11: r = __builtin_amdgcn_update_dpp(x, x, 0x15B, 0xF, 0xF, true); break;
+    case 12: r = __builtin_amdgcn_update_dpp(x, x, 0x15C, 0xF, 0xF, true); break;
+    case 13: r = __builtin_amdgcn_update_dpp(x, x, 0x15D, 0xF, 0xF, true); break;
+    case 14: r = __builtin_amdgcn_update_dpp(x, x, 0x15E, 0xF, 0xF, true); break;
+    default: r = __builtin_amdgcn_update_dpp(x, x, 0x15F, 0xF, 0xF, true); break;
   }
+  return __longlong_as_double(r);
+}
+
+// Update-and-shift, a[j] <- fma(-l, u[j], a[j + 1]) for the 16-column blocks
+// in use; the window's last element becomes zero.  The pivot row comes from
+// LDS one element per lane: lane c of every row of sixteen lanes reads
+// element c of a block, and the fma takes element e from lane e of its row
+// by DPP, so a block costs one 8-byte LDS read per lane instead of sixteen.
+// The next block is requested before the current block's fmas (the buffer is
+// padded to whole blocks).  Runs with every lane active (see row_bcast).
+template <int NB, int WC>
+__device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const double* u, int len, int c16) {
+  double ub[2];
+  ub[0] = u[c16];
 #pragma unroll
-  for (int c = 0; c < NBLK; ++c) {
-    if (BLK * c < len) {
-      if (c + 1 < NBLK) {
+  for (int b = 0; b < NB; ++b) {
+    if (16 * b < len) {
+      if (b + 1 < NB) ub[(b + 1) & 1] = u[16 * (b + 1) + c16];
 #pragma unroll
-        for (int e = 0; e < BLK; e += 2) {
-          const double2 v = *reinterpret_cast<const double2*>(u + BLK * (c + 1) + e);
-          ub[(c + 1) & 1][e] = v.x;
-          ub[(c + 1) & 1][e + 1] = v.y;
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < BLK; ++e) {
-        const int j = BLK * c + e;
-        if (j + 1 < WC) a[j] = __builtin_fma(nl, ub[c & 1][e], a[j + 1]);
+      for (int e = 0; e < 16; ++e) {
+        const int j = 16 * b + e;
+        if (j + 1 < WC) a[j] = __builtin_fma(nl, row_bcast(ub[b & 1], e), a[j + 1]);
         else if (j < WC) a[j] = 0.0;
       }
     }
   }
 }
 
+// U storage: row k (k < N <= NMAX) holds NMAX + 3 - k doubles rounded up to
+// even (16-byte aligned rows), followed by padding for the update's read-ahead.
 template <int NMAX>
 constexpr int u_size() {
-  return NMAX * (NMAX + 7) / 2 + 8;  // sum over positions k < N <= NMAX of (NMAX + 3 - k)
+  int s = 0;
+  for (int k = 0; k < NMAX; ++k) s += (NMAX + 3 - k + 1) & ~1;
+  return s + 16 * ((NMAX + 4 + 15) / 16) + 32;
 }
 
-template <int NMAX, int WAVES, int BLK>
+template <int NMAX, int WAVES>
 __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
     const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr, const int32_t* gp_nbr,
     const int64_t* blk_ptr, const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* R,
-    const double* X, const double* gp_xyz, double C2, double q, double* dphi, int keep, const int64_t* lu_off,
+    const double* X, const double* gp_xyz, double C2, double q, double* dphi, float* dphi32, int keep,
+    const int64_t* lu_off,
     double* lu, int32_t* piv_out, double* gam, DevStatus* st) {
   constexpr int T = 64 * WAVES;
   constexpr int WC = NMAX + 4;   // window: matrix columns + 3 right-hand sides + 1 zero
-  constexpr int NBLK = (WC + BLK - 1) / BLK;
+  constexpr int NB = (WC + 15) / 16;  // blocks of sixteen columns
   constexpr int US = u_size<NMAX>();
   constexpr int LDSD = US;
-  static_assert(T >= NMAX && NMAX % 8 == 0 && BLK % 2 == 0, "shape");
-  __shared__ __align__(16) double lds[LDSD];            // the U rows
-  __shared__ __align__(16) double prow[2][WAVES][NBLK * BLK];  // candidate windows shifted by one: prow[j] = w[j+1]
-  __shared__ double cval[2][WAVES];
-  __shared__ double cpiv[2][WAVES];                     // candidate's w[0]
-  __shared__ unsigned ckey[2][WAVES];
+  static_assert(T >= NMAX && NMAX % 8 == 0, "shape");
+  struct __align__(16) Cand {
+    double v;      // |a_k| of the wave's candidate (-1: no active row)
+    unsigned key;  // (position << 8) | row
+    unsigned pad;
+  };
+  __shared__ __align__(16) double lds[LDSD];  // the U rows
+  __shared__ Cand cand[2][WAVES];
+  __shared__ int uoffs[NMAX];                 // start of U row k in lds
   __shared__ double xsol[3][NMAX];
   __shared__ int S[NMAX];
   __shared__ int rlo[NMAX];          // per support node: first id of its row window,
@@ -271,72 +305,79 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   int pos = t;              // current position of my row
   const bool real = t < N;  // padding rows never take part
   double* Lkeep = keep ? lu + lu_off[g] : nullptr;      // multipliers, column-major by original row
-  int uoff = 0;                                           // offset of U row k in lds
+  int uoff = 0;                                           // start of U row k in lds
 #pragma unroll 1
   for (int k = 0; k < N; ++k) {
-    const int buf = k & 1;
     const int len = NMAX + 3 - k;  // window elements in use (columns k..NMAX-1 and 3 rhs)
     const bool active = real && pos >= k;
     double v;
     unsigned key;
     wave_argmax(fabs(a[0]), active, ((unsigned)pos << 8) | (unsigned)t, &v, &key);
-    if ((key & 255u) == (unsigned)t) {  // this wave's candidate publishes its window
-      publish_window<NBLK, BLK, WC>(a, prow[buf][w], len);
-      cpiv[buf][w] = a[0];
-    }
-    if (lane == 0) {
-      cval[buf][w] = v;
-      ckey[buf][w] = key;
-    }
-    __syncthreads();
-    double best = cval[buf][0];
-    unsigned bkey = ckey[buf][0];
-    int bw = 0;
+    double best = v;
+    unsigned bkey = key;
+    if constexpr (WAVES > 1) {
+      const int buf = k & 1;
+      if (lane == 0) {
+        Cand c;
+        c.v = key == 0xFFFFFFFFu ? -1.0 : v;
+        c.key = key;
+        c.pad = 0;
+        cand[buf][w] = c;
+      }
+      __syncthreads();
+      best = cand[buf][0].v;
+      bkey = cand[buf][0].key;
 #pragma unroll
-    for (int i = 1; i < WAVES; ++i) {
-      const double v2 = cval[buf][i];
-      const unsigned k2 = ckey[buf][i];
-      const bool take = v2 > best || (v2 == best && k2 < bkey);
-      best = take ? v2 : best;
-      bkey = take ? k2 : bkey;
-      bw = take ? i : bw;
+      for (int i = 1; i < WAVES; ++i) {
+        const Cand c = cand[buf][i];
+        const bool take = c.v > best || (c.v == best && c.key < bkey);
+        best = take ? c.v : best;
+        bkey = take ? c.key : bkey;
+      }
+    } else {
+      if (key == 0xFFFFFFFFu) best = -1.0;
     }
     if (!(best > tiny)) {
       if (t == 0) flag_error(st, kFlagSingular, g);
       return;  // uniform: every thread saw the same best
     }
     const int prow_id = (int)(bkey & 255u), ppos = (int)(bkey >> 8);
-    if (t == 0) rowat[k] = prow_id;
+    double* urow = lds + uoff;  // urow[0] = u_kk, urow[1 + j] = pivot column k+1+j
+    if (t == prow_id) write_row<NB, WC>(a, urow, len);
+    if (t == 0) {
+      rowat[k] = prow_id;
+      uoffs[k] = uoff;
+    }
     if (t == prow_id) pos = k;
     else if (pos == k) pos = ppos;
-    if (real && pos > k) {
-      const double l = a[0] / cpiv[buf][bw];
-      if (keep) Lkeep[(int64_t)k * N + t] = l;
-      shift_update<NBLK, BLK, WC>(a, -l, prow[buf][bw], len);  // prow[j] = pivot column k+1+j
+    if constexpr (WAVES > 1) __syncthreads();
+    {
+      // every lane runs the update (the DPP broadcast reads all lanes); rows that
+      // are not eliminated this step take l = 0, which only shifts their windows
+      // (the pivot's window is already stored as its U row)
+      const bool upd = real && pos > k;
+      const double l = upd ? a[0] / urow[0] : 0.0;
+      if (keep && upd) Lkeep[(int64_t)k * N + t] = l;
+      shift_update<NB, WC>(a, -l, urow + 1, len, lane & 15);
     }
-    // keep the pivot's window as U row k, one element per thread; the buffer is
-    // not written again before the next step's barrier
-    if (t == 0) lds[uoff] = cpiv[buf][bw];
-    for (int i = t; i < len - 1; i += T) lds[uoff + 1 + i] = prow[buf][bw][i];
-    uoff += len;
+    uoff += (len + 1) & ~1;
   }
   __syncthreads();
 
   // ---- back substitution by position from the U rows, k descending ------------
-  // U row k starts at k (NMAX + 3) - k (k - 1) / 2; its element j is column k + j
-  // and its right-hand sides sit at NMAX - k + (0, 1, 2).
+  // U row k starts at uoffs[k]; its element j is column k + j and its
+  // right-hand sides sit at NMAX - k + (0, 1, 2).
   int my_off = 0;
   double bb[3] = {0.0, 0.0, 0.0};
   if (t < N) {
-    my_off = t * (NMAX + 3) - (t * (t - 1)) / 2;
+    my_off = uoffs[t];
 #pragma unroll
     for (int j = 0; j < 3; ++j) bb[j] = lds[my_off + (NMAX - t) + j];
   }
-  int koff = (N - 1) * (NMAX + 3) - ((N - 1) * (N - 2)) / 2;
 #pragma unroll 1
   for (int k = N - 1; k >= 0; --k) {
     if (t == k) {
-      const double ukk = lds[koff];
+      const double ukk = lds[my_off];
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         bb[j] = bb[j] / ukk;
@@ -349,7 +390,6 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
 #pragma unroll
       for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, xsol[j][k], bb[j]);
     }
-    koff -= (NMAX + 3 - (k - 1));
   }
   __syncthreads();
 
@@ -357,14 +397,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   for (int idx = t; idx < 3 * n; idx += T) {
     const int aa = idx / 3, j = idx - 3 * aa;
     dphi[3 * (b0 + aa) + j] = xsol[j][aa];
+    if (dphi32) dphi32[3 * (b0 + aa) + j] = (float)xsol[j][aa];
   }
   if (keep) {
     // U by position, column-major (U[c*N + p] = u_pc), after the multipliers
     double* U = Lkeep + (int64_t)N * N;
     if (t < N) {
-      const int off = t * (NMAX + 3) - (t * (t - 1)) / 2;
       for (int c = 0; c < N; ++c)
-        if (t <= c) U[(int64_t)c * N + t] = lds[off + (c - t)];
+        if (t <= c) U[(int64_t)c * N + t] = lds[my_off + (c - t)];
     }
     const int64_t o = b0 + 4 * g;
     for (int i = t; i < N; i += T) piv_out[o + i] = rowat[i];
@@ -375,13 +415,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   }
 }
 
-template <int NMAX, int WAVES, int BLK>
-rpim_status launch_one(rpim_plan* p, const Bucket& bk, const double* X, double C2, int keep, hipStream_t s) {
-  hipLaunchKernelGGL((k_shape_win<NMAX, WAVES, BLK>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
+template <int NMAX, int WAVES>
+rpim_status launch_one(rpim_plan* p, const Bucket& bk, const double* X, double C2, int keep, float* dphi32,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_shape_win<NMAX, WAVES>), dim3((unsigned)bk.count), dim3(64 * WAVES), 0, s,
                      (const int32_t*)p->gp_order, bk.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
                      (const int64_t*)p->blk_ptr, (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off,
                      (const uint2*)p->rbm, (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, p->dphi,
-                     keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
+                     dphi32, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
   RPIM_HIP(hipGetLastError());
   return RPIM_OK;
 }
@@ -391,20 +432,21 @@ rpim_status launch_one(rpim_plan* p, const Bucket& bk, const double* X, double C
 // Largest padded size handled in registers; bigger buckets use the LDS kernel.
 int shape_reg_max() { return 104; }
 
-rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, hipStream_t s) {
+rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, float* dphi32,
+                             hipStream_t s) {
   switch (b.nmax) {
-    case 8: case 16: return launch_one<16, 1, 16>(p, b, X, C2, keep, s);
-    case 24: return launch_one<24, 1, 16>(p, b, X, C2, keep, s);
-    case 32: return launch_one<32, 1, 16>(p, b, X, C2, keep, s);
-    case 40: return launch_one<40, 1, 16>(p, b, X, C2, keep, s);
-    case 48: return launch_one<48, 1, 16>(p, b, X, C2, keep, s);
-    case 56: return launch_one<56, 1, 16>(p, b, X, C2, keep, s);
-    case 64: return launch_one<64, 1, 16>(p, b, X, C2, keep, s);
-    case 72: return launch_one<72, 2, 8>(p, b, X, C2, keep, s);
-    case 80: return launch_one<80, 2, 8>(p, b, X, C2, keep, s);
-    case 88: return launch_one<88, 2, 8>(p, b, X, C2, keep, s);
-    case 96: return launch_one<96, 2, 8>(p, b, X, C2, keep, s);
-    case 104: return launch_one<104, 2, 8>(p, b, X, C2, keep, s);
+    case 8: case 16: return launch_one<16, 1>(p, b, X, C2, keep, dphi32, s);
+    case 24: return launch_one<24, 1>(p, b, X, C2, keep, dphi32, s);
+    case 32: return launch_one<32, 1>(p, b, X, C2, keep, dphi32, s);
+    case 40: return launch_one<40, 1>(p, b, X, C2, keep, dphi32, s);
+    case 48: return launch_one<48, 1>(p, b, X, C2, keep, dphi32, s);
+    case 56: return launch_one<56, 1>(p, b, X, C2, keep, dphi32, s);
+    case 64: return launch_one<64, 1>(p, b, X, C2, keep, dphi32, s);
+    case 72: return launch_one<72, 2>(p, b, X, C2, keep, dphi32, s);
+    case 80: return launch_one<80, 2>(p, b, X, C2, keep, dphi32, s);
+    case 88: return launch_one<88, 2>(p, b, X, C2, keep, dphi32, s);
+    case 96: return launch_one<96, 2>(p, b, X, C2, keep, dphi32, s);
+    case 104: return launch_one<104, 2>(p, b, X, C2, keep, dphi32, s);
     default: return RPIM_E_RANGE;
   }
 }
