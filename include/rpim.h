@@ -164,6 +164,29 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
                                   const double* u_bar, int64_t n_fixed, double factor, double* rhs,
                                   double* alpha_out, void* stream);
 
+/* Launch-configuration tuning (synchronous).  Evaluates the pair table and the
+ * moment-matrix solves once, then times the row gather of `precision` with 2,
+ * 3 and 4 waves per node row on this plan's own data and keeps the fastest for
+ * later rpim_assemble calls with that precision (each configuration computes
+ * the same bits; only speed differs).  K_vals (nnz values of the precision's
+ * type) serves as scratch and is overwritten.  It also times each
+ * support-size bucket's solver launch, for the report only.  `out` may be
+ * NULL.  Supports and pattern must be built (RPIM_E_STATE otherwise). */
+#define RPIM_TUNING_MAX_BUCKETS 32
+typedef struct {
+  int32_t gather_waves;                          /* chosen: 2, 3 or 4              */
+  float gather_ms[3];                            /* row gather with 2, 3, 4 waves  */
+  int32_t n_buckets;                             /* buckets reported (<= 32)       */
+  int32_t bucket_nmax[RPIM_TUNING_MAX_BUCKETS];  /* padded size N of each bucket   */
+  int64_t bucket_points[RPIM_TUNING_MAX_BUCKETS];
+  float bucket_ms[RPIM_TUNING_MAX_BUCKETS];      /* solver launch time             */
+} rpim_tuning;
+rpim_status rpim_autotune(rpim_plan* plan, const double* node_xyz, const double* cell_E, double nu, int precision,
+                          void* K_vals, void* stream, rpim_tuning* out);
+/* Set the row-gather configuration (2, 3 or 4 waves per node row) for
+ * `precision` by hand, as rpim_autotune would; RPIM_E_ARG otherwise. */
+rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
+
 /* Synchronise `stream` and report device-side errors of the plan's last calls:
  * the most severe status and the smallest failing Gauss-point id (-1 if none).
  * Clears the record. */

@@ -36,6 +36,15 @@ class _Problem(C.Structure):
                 ("alpha_c", C.c_double), ("d_c", C.c_double), ("q", C.c_double)]
 
 
+_TUNING_MAX = 32
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("gather_waves", C.c_int32), ("gather_ms", C.c_float * 3), ("n_buckets", C.c_int32),
+                ("bucket_nmax", C.c_int32 * _TUNING_MAX), ("bucket_points", C.c_int64 * _TUNING_MAX),
+                ("bucket_ms", C.c_float * _TUNING_MAX)]
+
+
 class _Info(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_gp", C.c_int64), ("n_cells", C.c_int64), ("n_models", C.c_int64),
                 ("sum_n", C.c_int64), ("nnz", C.c_int64), ("n_blocks", C.c_int64), ("min_n", C.c_int32),
@@ -70,13 +79,15 @@ def lib():
         L.rpim_rebuild_pattern.argtypes = [vp, vp, vp, vp, C.POINTER(i64), vp]
         L.rpim_profile_enable.argtypes = [vp, i32]
         L.rpim_profile_read.argtypes = [vp, C.POINTER(d)]
+        L.rpim_autotune.argtypes = [vp, vp, vp, d, i32, vp, vp, C.POINTER(_Tuning)]
+        L.rpim_set_gather_waves.argtypes = [vp, i32, i32]
         L.rpim_plan_destroy.argtypes = [vp]
         L.rpim_plan_destroy.restype = None
         L.rpim_status_string.restype = C.c_char_p
         for f in ("rpim_plan_create", "rpim_build_pattern", "rpim_assemble", "rpim_assemble_backward",
                   "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
                   "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
-                  "rpim_profile_read"):
+                  "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -204,6 +215,29 @@ class Plan:
         inf = _Info()
         _check(lib().rpim_plan_info(self._h, C.byref(inf)), "rpim_plan_info")
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def autotune(self, node_xyz=None, cell_E=None, nu=0.3, precision=FP64, out=None) -> dict:
+        """Choose the row-gather launch configuration for `precision` by timing the candidates on
+        this plan (synchronous; `out`, or a temporary K buffer, is overwritten).  Returns the timings."""
+        torch = _torch()
+        if self.nnz is None:
+            self.build_pattern()
+        X = self.node_xyz if node_xyz is None else _dev(node_xyz, torch.float64, self.device)
+        E = _dev(cell_E, torch.float64, self.device)
+        prec = _precision(precision)
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64 if prec == FP64 else torch.float32, device=self.device)
+        t = _Tuning()
+        _check(lib().rpim_autotune(self._h, _ptr(X), _ptr(E), float(nu), prec, _ptr(out), _stream(), C.byref(t)),
+               "rpim_autotune")
+        n = t.n_buckets
+        return {"gather_waves": t.gather_waves,
+                "gather_ms": {w: t.gather_ms[w - 2] for w in (2, 3, 4)},
+                "buckets": [{"nmax": t.bucket_nmax[i], "points": t.bucket_points[i], "ms": t.bucket_ms[i]}
+                            for i in range(n)]}
+
+    def set_gather_waves(self, precision, waves: int):
+        _check(lib().rpim_set_gather_waves(self._h, _precision(precision), int(waves)), "rpim_set_gather_waves")
 
     # -- forward / backward ----------------------------------------------------
     def assemble(self, node_xyz=None, cell_E=None, nu=0.3, precision=FP64, keep_factors=False, out=None):

@@ -265,6 +265,72 @@ rpim_status rpim_assemble_backward(rpim_plan* p, const double* node_xyz, const d
   return launch_backward(p, node_xyz, cell_E, nu, dK_vals, dE_cell, dX_node, (hipStream_t)stream);
 }
 
+rpim_status rpim_autotune(rpim_plan* p, const double* node_xyz, const double* cell_E, double nu, int precision,
+                          void* K_vals, void* stream, rpim_tuning* out) {
+  if (!p || !node_xyz || !cell_E || !K_vals) return RPIM_E_ARG;
+  if (!p->built) return RPIM_E_STATE;
+  if (precision != RPIM_FP64 && precision != RPIM_MIXED) return RPIM_E_ARG;
+  if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  rpim_status st;
+  if ((st = ensure(&p->R, &p->cap_R, p->nblk)) || (st = ensure(&p->dphi, &p->cap_dphi, 3 * p->sum_n))) return st;
+  if (precision == RPIM_MIXED && (st = ensure(&p->dphi32, &p->cap_dphi32, 3 * p->sum_n))) return st;
+  float* d32 = precision == RPIM_MIXED ? p->dphi32 : nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  RPIM_HIP(hipEventCreate(&e0));
+  if (hip_ok(hipEventCreate(&e1)) != RPIM_OK) {
+    (void)hipEventDestroy(e0);
+    return RPIM_E_HIP;
+  }
+  auto timed = [&](auto&& launch, float* ms) -> rpim_status {
+    hipError_t e = hipEventRecord(e0, s);
+    rpim_status r = e == hipSuccess ? launch() : hip_ok(e);
+    if (r == RPIM_OK) r = hip_ok(hipEventRecord(e1, s));
+    if (r == RPIM_OK) r = hip_ok(hipEventSynchronize(e1));
+    if (r == RPIM_OK) r = hip_ok(hipEventElapsedTime(ms, e0, e1));
+    return r;
+  };
+  rpim_tuning t = {};
+  st = launch_pair_table(p, node_xyz, s);
+  int nb = 0;
+  for (const Bucket& b : p->buckets) {
+    if (st != RPIM_OK) break;
+    float ms = 0.f;
+    st = timed([&] { return launch_shape_bucket(p, b, node_xyz, 0, d32, s); }, &ms);
+    if (nb < RPIM_TUNING_MAX_BUCKETS) {
+      t.bucket_nmax[nb] = b.nmax;
+      t.bucket_points[nb] = b.count;
+      t.bucket_ms[nb] = ms;
+      ++nb;
+    }
+  }
+  t.n_buckets = nb;
+  int best = 0;
+  for (int i = 0; i < 3 && st == RPIM_OK; ++i) {
+    const int gw = 2 + i;
+    float ms = 0.f, best_ms = 0.f;
+    for (int rep = 0; rep < 3 && st == RPIM_OK; ++rep) {  // first run warms caches and sets LDS limits
+      st = timed([&] { return launch_rowgather(p, cell_E, nu, precision, K_vals, s, gw); }, &ms);
+      if (rep == 1 || (rep > 1 && ms < best_ms)) best_ms = ms;
+    }
+    t.gather_ms[i] = best_ms;
+    if (best_ms < t.gather_ms[best]) best = i;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != RPIM_OK) return st;
+  t.gather_waves = 2 + best;
+  p->gather_waves[precision == RPIM_MIXED ? 1 : 0] = t.gather_waves;
+  if (out) *out = t;
+  return RPIM_OK;
+}
+
+rpim_status rpim_set_gather_waves(rpim_plan* p, int precision, int waves) {
+  if (!p || (precision != RPIM_FP64 && precision != RPIM_MIXED) || !gather_waves_valid(waves)) return RPIM_E_ARG;
+  p->gather_waves[precision == RPIM_MIXED ? 1 : 0] = waves;
+  return RPIM_OK;
+}
+
 rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, int precision,
                                   int64_t n_dof, const int32_t* fixed_dof, const double* u_bar, int64_t n_fixed,
                                   double factor, double* rhs, double* alpha_out, void* stream) {

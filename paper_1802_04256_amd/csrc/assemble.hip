@@ -224,18 +224,15 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 
 // ---- row gather: one workgroup per node row I --------------------------------
 // acc[pos][9] over the row's column blocks (pos = rank of J in row I).  The
-// row's columns are cut into kGatherWaves ranges of node ids and wave w owns
+// row's columns are cut into GW ranges of node ids and wave w owns
 // the slots of its range, so no slot is touched by two waves.  Each wave walks
 // the row's Gauss points in ascending g; since supports are sorted, the part
 // of a point's support inside the wave's range is a contiguous run, found with
 // two ballots, and its entries go one per lane, each lane adding all nine
 // entries of its 3x3 block.  A wave's LDS accesses execute in program order,
 // so every slot receives its contributions in ascending g without barriers.
-constexpr int kGatherWaves = 2;
-constexpr int kGatherThreads = 64 * kGatherWaves;
-
-template <bool kMixed>
-__global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
+template <bool kMixed, int GW>
+__global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
                                                               const int32_t* row_lo,
                                                               const int64_t* rbm_off, const uint2* rbm,
                                                               const int64_t* inv_ptr, const uint64_t* inv_key,
@@ -257,11 +254,12 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
   const int lo_I = row_lo[I];
   const int64_t wb = rbm_off[I];
   const int nw = (int)(rbm_off[I + 1] - wb);
-  for (int i = tid; i < nw; i += kGatherThreads) bm[i] = rbm[wb + i];
-  for (int i = tid; i < 9 * L; i += kGatherThreads) acc[i] = 0.0;
+  constexpr int kThreadsG = 64 * GW;
+  for (int i = tid; i < nw; i += kThreadsG) bm[i] = rbm[wb + i];
+  for (int i = tid; i < 9 * L; i += kThreadsG) acc[i] = 0.0;
   // this wave's columns: node ids in [thr_lo, thr_hi)
-  const int32_t thr_lo = w == 0 ? INT_MIN : blk_col[rb + (int64_t)w * L / kGatherWaves];
-  const int32_t thr_hi = w + 1 == kGatherWaves ? INT_MAX : blk_col[rb + (int64_t)(w + 1) * L / kGatherWaves];
+  const int32_t thr_lo = w == 0 ? INT_MIN : blk_col[rb + (int64_t)w * L / GW];
+  const int32_t thr_hi = w + 1 == GW ? INT_MAX : blk_col[rb + (int64_t)(w + 1) * L / GW];
   __syncthreads();
 
   // Software pipeline over the row's Gauss points: point metadata (scalar)
@@ -394,7 +392,7 @@ __global__ void __launch_bounds__(kGatherThreads) k_rowgather(const int64_t* blk
   }
   __syncthreads();
   const int64_t base = 9 * rb;
-  for (int idx = tid; idx < 9 * L; idx += kGatherThreads) {
+  for (int idx = tid; idx < 9 * L; idx += kThreadsG) {
     const int pos = idx / 9, r = idx - 9 * pos, a = r / 3, be = r - 3 * a;
     const int64_t o = base + 3 * (int64_t)a * L + 3 * pos + be;
     if (!kMixed) ((double*)Kout)[o] = acc[idx];
@@ -413,7 +411,7 @@ rpim_status lds_limit(const void* fn, size_t lds, size_t* cur) {
   *cur = lds;
   return RPIM_OK;
 }
-size_t g_lds_shape = 0, g_lds_gather64 = 0, g_lds_gather32 = 0;
+size_t g_lds_shape = 0;
 
 }  // namespace
 
@@ -427,33 +425,51 @@ rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s) {
   return RPIM_OK;
 }
 
-rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s) {
+rpim_status launch_shape_bucket(rpim_plan* p, const Bucket& b, const double* X, int keep, float* dphi32,
+                                hipStream_t s) {
   const double ac = p->alpha_c * p->d_c;
   const double C2 = ac * ac;
   const char* sel = getenv("RPIM_SHAPE_KERNEL");
   const bool use_reg = !(sel && sel[0] == 'l');  // "lds" selects the shared-memory kernel for every bucket
-  for (const Bucket& b : p->buckets) {
-    if (use_reg && b.nmax <= shape_reg_max()) {
-      rpim_status st = launch_shape_reg(p, b, X, C2, keep, dphi32, s);
-      if (st != RPIM_OK) return st;
-      continue;
-    }
-    const int N = b.nmax;
-    const int ld = ((N + 3) | 1);  // odd row stride in doubles
-    const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
-    if (lds > 160 * 1024) return RPIM_E_RANGE;
-    if (rpim_status st = lds_limit((const void*)k_shape, lds, &g_lds_shape)) return st;
-    hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
-                       b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
-                       (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
-                       p->dphi, dphi32, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
-    RPIM_HIP(hipGetLastError());
-  }
+  if (use_reg && b.nmax <= shape_reg_max()) return launch_shape_reg(p, b, X, C2, keep, dphi32, s);
+  const int N = b.nmax;
+  const int ld = ((N + 3) | 1);  // odd row stride in doubles
+  const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
+  if (lds > 160 * 1024) return RPIM_E_RANGE;
+  if (rpim_status st = lds_limit((const void*)k_shape, lds, &g_lds_shape)) return st;
+  hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
+                     b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
+                     (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
+                     (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q, ld,
+                     p->dphi, dphi32, keep, (const int64_t*)p->lu_off, p->lu, p->piv, p->gam, p->status);
+  RPIM_HIP(hipGetLastError());
   return RPIM_OK;
 }
 
-rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s) {
+rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s) {
+  for (const Bucket& b : p->buckets)
+    if (rpim_status st = launch_shape_bucket(p, b, X, keep, dphi32, s)) return st;
+  return RPIM_OK;
+}
+
+template <bool kMixed, int GW>
+rpim_status launch_gather_t(rpim_plan* p, const double* E, double lam, double mu, void* K, size_t lds, hipStream_t s) {
+  static size_t lds_set = 0;
+  if (rpim_status st = lds_limit((const void*)k_rowgather<kMixed, GW>, lds, &lds_set)) return st;
+  hipLaunchKernelGGL((k_rowgather<kMixed, GW>), dim3((unsigned)p->N), dim3(64 * GW), lds, s,
+                     (const int64_t*)p->blk_ptr, (const int32_t*)p->blk_col, (const int32_t*)p->row_lo,
+                     (const int64_t*)p->rbm_off, (const uint2*)p->rbm, (const int64_t*)p->inv_ptr,
+                     (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
+                     kMixed ? (const void*)p->dphi32 : (const void*)p->dphi, (const double*)p->gp_wdet,
+                     (const int32_t*)p->gp_cell, E, lam, mu, K);
+  RPIM_HIP(hipGetLastError());
+  return RPIM_OK;
+}
+
+int gather_waves_valid(int gw) { return gw == 2 || gw == 3 || gw == 4; }
+
+rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s,
+                             int gather_waves) {
   const double onep = 1.0 + nu;
   const double onem = 1.0 - 2.0 * nu;
   const double lam = nu / (onep * onem);
@@ -461,25 +477,19 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   const int L = (int)p->max_row_blocks;
   const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds > 160 * 1024) return RPIM_E_RANGE;
+  const int gw = gather_waves > 0 ? gather_waves : p->gather_waves[precision == RPIM_MIXED ? 1 : 0];
   if (precision == RPIM_FP64) {
-    if (rpim_status st = lds_limit((const void*)k_rowgather<false>, lds, &g_lds_gather64)) return st;
-    hipLaunchKernelGGL(k_rowgather<false>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col,
-                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
-                       (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
-                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const void*)p->dphi,
-                       (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
-  } else {
-    if (rpim_status st = lds_limit((const void*)k_rowgather<true>, lds, &g_lds_gather32)) return st;
-    hipLaunchKernelGGL(k_rowgather<true>, dim3((unsigned)p->N), dim3(kGatherThreads), lds, s, (const int64_t*)p->blk_ptr,
-                       (const int32_t*)p->blk_col,
-                       (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
-                       (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
-                       (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const void*)p->dphi32,
-                       (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, K);
+    switch (gw) {
+      case 3: return launch_gather_t<false, 3>(p, E, lam, mu, K, lds, s);
+      case 4: return launch_gather_t<false, 4>(p, E, lam, mu, K, lds, s);
+      default: return launch_gather_t<false, 2>(p, E, lam, mu, K, lds, s);
+    }
   }
-  RPIM_HIP(hipGetLastError());
-  return RPIM_OK;
+  switch (gw) {
+    case 3: return launch_gather_t<true, 3>(p, E, lam, mu, K, lds, s);
+    case 4: return launch_gather_t<true, 4>(p, E, lam, mu, K, lds, s);
+    default: return launch_gather_t<true, 2>(p, E, lam, mu, K, lds, s);
+  }
 }
 
 rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s) {

@@ -117,6 +117,9 @@ struct rpim_plan {
 
   rpim::DevStatus* status = nullptr;
 
+  // launch configurations chosen by rpim_autotune (defaults until then)
+  int gather_waves[2] = {2, 2};  // row-gather waves per node row: [FP64, mixed]
+
   // capacities (elements) of the workspaces above, so a rebuilt pattern can reuse them
   int64_t cap_R = 0, cap_dphi = 0, cap_dphi32 = 0, cap_lu = 0, cap_piv = 0, cap_gam = 0;
   int64_t cap_msym = 0, cap_pbar = 0, cap_dEs = 0, cap_dEg = 0, cap_dXs = 0;
@@ -160,8 +163,12 @@ rpim_status expand_pattern(const rpim_plan* p, int64_t* row_ptr, int32_t* col_id
 rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s);
 // dphi32 (may be null): also write the gradients rounded to float, for the mixed-precision gather
 rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s);
-rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K,
-                             hipStream_t s);
+rpim_status launch_shape_bucket(rpim_plan* p, const Bucket& b, const double* X, int keep, float* dphi32,
+                                hipStream_t s);
+// gather_waves: waves per row of the gather (2, 3 or 4), 0 = the plan's tuned choice
+rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s,
+                             int gather_waves = 0);
+int gather_waves_valid(int gw);
 int shape_reg_max();
 rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, float* dphi32,
                              hipStream_t s);

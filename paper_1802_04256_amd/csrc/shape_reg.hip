@@ -76,9 +76,19 @@ __device__ __forceinline__ void wave_argmax(double ax, bool active, unsigned key
   const unsigned hi = active ? (unsigned)(bits >> 32) : 0u;
   const unsigned lo = (unsigned)bits;
   const unsigned mhi = wave_reduce_u32<true>(hi);
-  const unsigned mlo = wave_reduce_u32<true>((active && hi == mhi) ? lo : 0u);
-  const bool cand = active && hi == mhi && lo == mlo;
-  const unsigned mkey = wave_reduce_u32<false>(cand ? key : 0xFFFFFFFFu);
+  // usually a single lane holds the largest high word: it is the winner, and
+  // the low-word and key passes (which only break ties) are skipped
+  const unsigned long long c1 = __ballot(active && hi == mhi);
+  unsigned mlo, mkey;
+  if (__popcll(c1) == 1) {
+    const int L = __ffsll((long long)c1) - 1;
+    mlo = (unsigned)__builtin_amdgcn_readlane((int)lo, L);
+    mkey = (unsigned)__builtin_amdgcn_readlane((int)key, L);
+  } else {
+    mlo = wave_reduce_u32<true>((active && hi == mhi) ? lo : 0u);
+    const bool cand = active && hi == mhi && lo == mlo;
+    mkey = wave_reduce_u32<false>(cand ? key : 0xFFFFFFFFu);
+  }
   *bkey = mkey;
   *best = (mkey == 0xFFFFFFFFu) ? -1.0 : __longlong_as_double(((unsigned long long)mhi << 32) | mlo);
 }

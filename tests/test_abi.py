@@ -48,6 +48,19 @@ def test_plan_create_rejects_bad_arguments():
     assert lib.rpim_assemble(None, None, None, ctypes.c_double(0.3), 0, 0, None, None) == -1
     assert lib.rpim_apply_penalty_bc(None, None, None, 0, 0, None, None, 0, ctypes.c_double(1.0), None, None,
                                      None) == -1
+    assert lib.rpim_autotune(None, None, None, ctypes.c_double(0.3), 0, None, None, None) == -1
+
+
+def test_tuning_struct_matches_header():
+    # the binding's ctypes mirror of rpim_tuning must agree with the header's layout
+    import paper_1802_04256_amd as rp
+    src = open(os.path.join(ROOT, "include", "rpim.h")).read()
+    end = src.index("} rpim_tuning;")
+    body = src[src.rindex("typedef struct {", 0, end):end]
+    fields = re.findall(r"\b(int32_t|int64_t|float)\s+(\w+)(\[[A-Z_0-9]+\])?;", body)
+    names = [f[1] for f in fields]
+    assert names == [f[0] for f in rp._Tuning._fields_]
+    assert int(re.search(r"#define RPIM_TUNING_MAX_BUCKETS (\d+)", src).group(1)) == rp._TUNING_MAX
 
 
 def test_package_has_no_cpu_fallback():

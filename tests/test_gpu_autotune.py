@@ -1,0 +1,37 @@
+"""Launch-configuration tuning: every row-gather configuration yields the same
+K bit for bit (FP64 and mixed), and rpim_autotune picks one of them, reports a
+timing for every support-size bucket and leaves results unchanged."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gather_configurations_agree_and_autotune(precision):
+    import torch
+    import paper_1802_04256_amd as rp
+    prob = W.slope(L=12.0, W=8.0, H=6.0, x_c=3.0)
+    print(f"[gpu case] autotune {precision}: gps={prob.n_gp}", flush=True)
+    plan = rp.Plan.from_problem(prob)
+    plan.build_pattern()
+    E = torch.from_numpy(prob.cell_E).cuda()
+    ref = plan.assemble(cell_E=E, nu=prob.nu, precision=precision).cpu().numpy()
+    for waves in (2, 3, 4):
+        plan.set_gather_waves(precision, waves)
+        K = plan.assemble(cell_E=E, nu=prob.nu, precision=precision).cpu().numpy()
+        assert np.array_equal(K, ref), waves
+    with pytest.raises(rp.RpimError):
+        plan.set_gather_waves(precision, 5)
+    t = plan.autotune(cell_E=E, nu=prob.nu, precision=precision)
+    print(t)
+    assert t["gather_waves"] in (2, 3, 4)
+    assert all(v > 0 for v in t["gather_ms"].values())
+    info = plan.info()
+    assert len(t["buckets"]) == info["n_buckets"]
+    assert sum(b["points"] for b in t["buckets"]) == prob.n_gp
+    K = plan.assemble(cell_E=E, nu=prob.nu, precision=precision).cpu().numpy()
+    assert np.array_equal(K, ref)
+    plan.status()
