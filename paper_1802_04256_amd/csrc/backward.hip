@@ -153,6 +153,7 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   extern __shared__ double smem[];
   __shared__ double xg[3];
   const int tid = threadIdx.x;
+  const int nT = blockDim.x;  // 64 * ceil(N / 64): one thread per unknown, whole waves
   const int64_t g = gp_order[order_begin + blockIdx.x];
   const int64_t b0 = gp_ptr[g];
   const int n = (int)(gp_ptr[g + 1] - b0);
@@ -170,8 +171,8 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   const int64_t o = b0 + 4 * g;
   const double* Lm = lu + lu_off[g];      // multipliers [k][original row]
   const double* U = Lm + (int64_t)N * N;  // U column-major by position
-  for (int idx = tid; idx < 3 * N; idx += kT) gm[idx] = gam[3 * o + idx];
-  for (int i = tid; i < n; i += kT) {
+  for (int idx = tid; idx < 3 * N; idx += nT) gm[idx] = gam[3 * o + idx];
+  for (int i = tid; i < n; i += nT) {
     const int32_t sidx = gp_nbr[b0 + i];
     S[i] = sidx;
     rloS[i] = row_lo[sidx];
@@ -179,10 +180,10 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
     rbpS[i] = blk_ptr[sidx];
     for (int k = 0; k < 3; ++k) xs[3 * i + k] = X[3 * (int64_t)sidx + k];
   }
-  for (int i = tid; i < N; i += kT) rowat[i] = piv[o + i];
+  for (int i = tid; i < N; i += nT) rowat[i] = piv[o + i];
   if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
   __syncthreads();
-  for (int i = tid; i < N; i += kT) posf[rowat[i]] = i;
+  for (int i = tid; i < N; i += nT) posf[rowat[i]] = i;
   // right-hand side [Phibar_k; 0] of my original row
   const bool own = tid < N;
   double b[3] = {0.0, 0.0, 0.0};
@@ -259,7 +260,7 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   // table (symmetric bit for bit), four b at a time with the loads first: one
   // load instruction touches four rows (one per sub) at the columns of sixteen
   // consecutive support nodes.
-  for (int a0 = 0; a0 < n; a0 += kT / 4) {
+  for (int a0 = 0; a0 < n; a0 += nT / 4) {
     const int a = a0 + tid / 4, sub = tid & 3;
     double acc[3] = {0.0, 0.0, 0.0};
     if (a < n) {
@@ -402,7 +403,9 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   for (const Bucket& b : p->buckets) {
     const int N = b.nmax;
     const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(4 * N);
-    hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(kT), lds, s, (const int32_t*)p->gp_order, b.begin,
+    const int threads = 64 * ((N + 63) / 64);  // whole waves, at least one thread per unknown
+    if (threads > kT) return RPIM_E_RANGE;
+    hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(threads), lds, s, (const int32_t*)p->gp_order, b.begin,
                        (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                        (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                        (const double*)p->R, X, (const double*)p->gp_xyz, C2, p->q,
