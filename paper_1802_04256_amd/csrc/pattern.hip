@@ -235,12 +235,14 @@ __global__ void __launch_bounds__(256) k_window(int64_t N, const int64_t* inv_pt
   }
 }
 
-template <bool kFill>
-__global__ void __launch_bounds__(256) k_blocks(const int64_t* inv_ptr, const uint64_t* inv_key,
-                                                const int64_t* gp_ptr, const int32_t* gp_nbr,
-                                                const int32_t* win_lo, const int32_t* win_len, int words,
-                                                int32_t* blk_cnt, const int64_t* blk_ptr, int32_t* blk_col,
-                                                int32_t* blk_row, const int64_t* rbm_off, uint2* rbm) {
+// Union of the supports of every Gauss point whose support holds node I, as a
+// bitmap over I's node-id window: the words go to I's rank-bitmap slots (bits
+// only; the prefix counts follow in k_blocks_fill) and the set-bit count to
+// blk_cnt[I].
+__global__ void __launch_bounds__(256) k_blocks_union(const int64_t* inv_ptr, const uint64_t* inv_key,
+                                                      const int64_t* gp_ptr, const int32_t* gp_nbr,
+                                                      const int32_t* win_lo, const int32_t* win_len,
+                                                      int32_t* blk_cnt, const int64_t* rbm_off, uint2* rbm) {
   extern __shared__ unsigned bm[];
   const int64_t I = blockIdx.x;
   const int lo = win_lo[I];
@@ -257,29 +259,45 @@ __global__ void __launch_bounds__(256) k_blocks(const int64_t* inv_ptr, const ui
     }
   }
   __syncthreads();
+  int cnt = 0;
+  const int64_t w_beg = rbm_off[I];
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) {
+    rbm[w_beg + i] = make_uint2(bm[i], 0u);
+    cnt += __popc(bm[i]);
+  }
+  __shared__ int part[256];
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) blk_cnt[I] = part[0];
+}
+
+// Expand row I's bitmap into its sorted columns and set each word's prefix
+// count (position of J in row I = prefix + popc(bits below J)).
+__global__ void __launch_bounds__(256) k_blocks_fill(const int32_t* win_lo, const int64_t* blk_ptr, int32_t* blk_col,
+                                                     int32_t* blk_row, const int64_t* rbm_off, uint2* rbm) {
+  const int64_t I = blockIdx.x;
+  const int lo = win_lo[I];
+  const int64_t w_beg = rbm_off[I];
+  const int nw = (int)(rbm_off[I + 1] - w_beg);
   // each thread owns a contiguous run of words
   const int per = (nw + blockDim.x - 1) / blockDim.x;
   const int w0 = threadIdx.x * per, w1 = min(w0 + per, nw);
   int cnt = 0;
-  for (int i = w0; i < w1; ++i) cnt += __popc(bm[i]);
+  for (int i = w0; i < w1; ++i) cnt += __popc(rbm[w_beg + i].x);
   __shared__ int part[256];
   part[threadIdx.x] = cnt;
   __syncthreads();
-  if (!kFill) {
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) blk_cnt[I] = part[0];
-    return;
-  }
   int pos = 0;
   for (int t = 0; t < (int)threadIdx.x; ++t) pos += part[t];
   const int64_t out = blk_ptr[I] + pos;
   int k = 0;
   for (int i = w0; i < w1; ++i) {
-    unsigned v = bm[i];
-    rbm[rbm_off[I] + i] = make_uint2(v, (unsigned)(pos + k));
+    unsigned v = rbm[w_beg + i].x;
+    rbm[w_beg + i].y = (unsigned)(pos + k);
     while (v) {
       const int bit = __ffs(v) - 1;
       v &= v - 1;
@@ -460,11 +478,10 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     RPIM_HIP(hipMalloc((void**)&p->rbm, sizeof(uint2) * std::max<int64_t>(off[N], 1)));
     RPIM_HIP(hipMemcpyAsync(p->rbm_off, off.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice, s));
   }
-  hipLaunchKernelGGL(k_blocks<false>, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
+  hipLaunchKernelGGL(k_blocks_union, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr,
-                     (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, words, blk_cnt,
-                     (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr, (const int64_t*)nullptr,
-                     (uint2*)nullptr);
+                     (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, blk_cnt,
+                     (const int64_t*)p->rbm_off, p->rbm);
   RPIM_HIP(hipGetLastError());
   RPIM_HIP(hipMalloc((void**)&p->blk_ptr, sizeof(int64_t) * (N + 1)));
   st = exclusive_scan(blk_cnt, N, p->blk_ptr, s);
@@ -479,11 +496,8 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   for (int64_t i = 0; i < N; ++i) p->max_row_blocks = std::max<int64_t>(p->max_row_blocks, cnt_h[i]);
   RPIM_HIP(hipMalloc((void**)&p->blk_col, sizeof(int32_t) * nblk));
   RPIM_HIP(hipMalloc((void**)&p->blk_row, sizeof(int32_t) * nblk));
-  hipLaunchKernelGGL(k_blocks<true>, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
-                     (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr,
-                     (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, words,
-                     (int32_t*)nullptr, (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row,
-                     (const int64_t*)p->rbm_off, p->rbm);
+  hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)N), dim3(256), 0, s, (const int32_t*)win_lo,
+                     (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row, (const int64_t*)p->rbm_off, p->rbm);
   RPIM_HIP(hipGetLastError());
 
   // buckets by padded moment-matrix size, and LU offsets (host, from gp_ptr)
