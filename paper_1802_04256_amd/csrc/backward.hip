@@ -15,8 +15,8 @@
 // (M's row held in LDS) producing Phibar and the dE share for every slot
 // (g, local index of I); (3) one workgroup per Gauss point for the adjoint
 // solves and the chain rule, writing per-slot coordinate gradients;
-// (4) deterministic reductions of the slots to nodes (ascending g) and to
-// cells (ascending g).  No atomics.
+// (4) deterministic reductions of the slots to nodes (fixed-order per-lane
+// sums and butterfly) and to cells (ascending g).  No atomics.
 #include <cfloat>
 
 #include "dd_pow.h"
@@ -331,21 +331,33 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   }
 }
 
-__global__ void k_reduce_nodes(int64_t N, const int64_t* inv_ptr, const uint64_t* inv_key, const int64_t* gp_ptr,
-                               const double* dXs, double* dX) {
-  const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= N) return;
+// dL/dx of node I: sum of its slots' contributions.  One wave per node: lane l
+// sums entries l, l + 64, ... in ascending order, then a fixed butterfly adds
+// the lanes (deterministic, no atomics).
+__global__ void __launch_bounds__(256) k_reduce_nodes(int64_t N, const int64_t* inv_ptr, const uint64_t* inv_key,
+                                                      const int64_t* gp_ptr, const double* dXs, double* dX) {
+  const int64_t I = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (I >= N) return;  // uniform per wave
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int64_t e = inv_ptr[I]; e < inv_ptr[I + 1]; ++e) {
+  for (int64_t e = inv_ptr[I] + lane; e < inv_ptr[I + 1]; e += 64) {
     const uint64_t key = inv_key[e];
     const int64_t slot = gp_ptr[(int64_t)(key >> 8)] + (int64_t)(key & 255);
     s0 += dXs[3 * slot];
     s1 += dXs[3 * slot + 1];
     s2 += dXs[3 * slot + 2];
   }
-  dX[3 * I] = s0;
-  dX[3 * I + 1] = s1;
-  dX[3 * I + 2] = s2;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if (lane == 0) {
+    dX[3 * I] = s0;
+    dX[3 * I + 1] = s1;
+    dX[3 * I + 2] = s2;
+  }
 }
 
 __global__ void k_reduce_gp(int64_t G, const int64_t* gp_ptr, const double* dEs, double* dEg) {
@@ -415,7 +427,7 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   }
   phase_end(p, RPIM_PHASE_BWD_GP, s);
   phase_begin(p, RPIM_PHASE_BWD_REDUCE, s);
-  hipLaunchKernelGGL(k_reduce_nodes, dim3(nblocks(p->N, 256)), dim3(256), 0, s, p->N, (const int64_t*)p->inv_ptr,
+  hipLaunchKernelGGL(k_reduce_nodes, dim3(nblocks(p->N, 4)), dim3(256), 0, s, p->N, (const int64_t*)p->inv_ptr,
                      (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const double*)p->dXs, dX);
   hipLaunchKernelGGL(k_reduce_gp, dim3(nblocks(p->G, 256)), dim3(256), 0, s, p->G, (const int64_t*)p->gp_ptr,
                      (const double*)p->dEs, p->dEg);
