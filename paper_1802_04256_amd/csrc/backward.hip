@@ -27,6 +27,22 @@ namespace {
 
 constexpr int kT = 256;
 
+// Sum over each row of sixteen lanes, delivered to the row's lane 15: an
+// inclusive scan with DPP row shifts (lanes shifted in from outside the row
+// read zero).  Fixed order, so deterministic; every lane must be active.
+__device__ __forceinline__ double row16_sum(double v) {
+  long long x;
+  x = __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x111, 0xF, 0xF, true);
+  v += __longlong_as_double(x);
+  x = __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x112, 0xF, 0xF, true);
+  v += __longlong_as_double(x);
+  x = __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x114, 0xF, 0xF, true);
+  v += __longlong_as_double(x);
+  x = __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x118, 0xF, 0xF, true);
+  v += __longlong_as_double(x);
+  return v;
+}
+
 __device__ __forceinline__ int64_t find_sorted(const int32_t* v, int64_t b, int64_t e, int32_t key) {
   while (b < e) {
     const int64_t m = (b + e) >> 1;
@@ -124,10 +140,8 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
       }
     }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) v[i] += __shfl_xor(v[i], o, 16);
-    if (live && ql == 0) {
+    for (int i = 0; i < 4; ++i) v[i] = row16_sum(v[i]);
+    if (live && ql == 15) {
       const int64_t slot = b0 + aI;
       pbar[3 * slot] = v[0];
       pbar[3 * slot + 1] = v[1];
