@@ -212,3 +212,34 @@ def test_batched_models_equal_individual(rp):
         r0 = 3 * batch.node_off[i]
         seg = Kb[rpb[r0]:rpb[r0 + 3 * mdl.n_nodes]]
         assert np.array_equal(seg, Ki)
+
+
+def test_large_supports_lds_kernel_bitwise(rp, oracle_mod):
+    # a wider support radius puts the largest supports past the register
+    # kernel's 104-row limit, into the LDS kernel
+    prob = W.box(n=8, p=2, jitter=0.3, jitter_seed=61, E_seed=62)
+    prob.support_radius = 2.9
+    print(f"[gpu case] box8 radius 2.9: nodes={prob.n_nodes} gps={prob.n_gp}", flush=True)
+    m, plan = _both(prob, oracle_mod, rp)
+    info = plan.info()
+    assert info["max_n"] + 4 > 104, info["max_n"]
+    gp_ptr, gp_nbr = m.support()
+    assert np.array_equal(plan.support()[1].cpu().numpy(), gp_nbr)
+    K = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
+    plan.status()
+    assert np.array_equal(plan.dphi().cpu().numpy(), np.concatenate([m.shape(g)[1] for g in range(prob.n_gp)]))
+    assert np.array_equal(K, m.assemble())
+
+
+def test_lds_kernel_equals_register_kernel(rp, monkeypatch):
+    prob = W.slope(L=12.0, W=8.0, H=6.0, x_c=3.0, jitter_seed=71, E_seed=72)
+    plan = rp.Plan.from_problem(prob)
+    plan.build_pattern()
+    K_reg = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
+    d_reg = plan.dphi().cpu().numpy()
+    monkeypatch.setenv("RPIM_SHAPE_KERNEL", "lds")
+    K_lds = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
+    d_lds = plan.dphi().cpu().numpy()
+    plan.status()
+    assert np.array_equal(d_reg, d_lds)
+    assert np.array_equal(K_reg, K_lds)
