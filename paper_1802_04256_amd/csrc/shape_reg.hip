@@ -169,6 +169,14 @@ __device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const d
   }
 }
 
+// 64-bit readlane: lane L's value of x (L wave-uniform).
+__device__ __forceinline__ double readlane_f64(double x, int L) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, L);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // U storage: row k (k < N <= NMAX) holds NMAX + 3 - k doubles rounded up to
 // even (16-byte aligned rows), followed by padding for the update's read-ahead.
 template <int NMAX>
@@ -375,31 +383,67 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   __syncthreads();
 
   // ---- back substitution by position from the U rows, k descending ------------
-  // U row k starts at uoffs[k]; its element j is column k + j and its
-  // right-hand sides sit at NMAX - k + (0, 1, 2).
+  // Thread t holds position t: U row t starts at uoffs[t], its element j is
+  // column t + j and its right-hand sides sit at NMAX - t + (0, 1, 2).  At
+  // step k the thread at position k forms x_k = b_k / u_kk; the other threads
+  // of its wave take x_k by readlane (no barrier), and threads t < k update
+  // b_t <- fma(-u_tk, x_k, b_t).  With two waves, positions 64 and up belong
+  // to wave 1, which runs them first on its own; after one barrier wave 0
+  // applies those x_k in the same descending order and finishes.
   int my_off = 0;
   double bb[3] = {0.0, 0.0, 0.0};
+  double ud = 1.0;
   if (t < N) {
     my_off = uoffs[t];
+    ud = lds[my_off];
 #pragma unroll
     for (int j = 0; j < 3; ++j) bb[j] = lds[my_off + (NMAX - t) + j];
   }
-#pragma unroll 1
-  for (int k = N - 1; k >= 0; --k) {
-    if (t == k) {
-      const double ukk = lds[my_off];
+  double myx[3] = {0.0, 0.0, 0.0};  // thread t: x at position t
+  const auto bsub_step = [&](int k) {
+    const int src = k & 63;
+    const double urk = t < k ? lds[my_off + (k - t)] : 0.0;
+    const double ukk = readlane_f64(ud, src);
+    double x[3];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        bb[j] = bb[j] / ukk;
-        xsol[j][k] = bb[j];
+    for (int j = 0; j < 3; ++j) x[j] = readlane_f64(bb[j], src) / ukk;
+    if (t == k) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) myx[j] = x[j];
+    }
+    if (t < k) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, x[j], bb[j]);
+    }
+  };
+  if constexpr (WAVES == 1) {
+#pragma unroll 1
+    for (int k = N - 1; k >= 0; --k) bsub_step(k);
+  } else {
+    static_assert(WAVES == 2, "waves");
+    if (w == 1) {
+#pragma unroll 1
+      for (int k = N - 1; k >= 64; --k) bsub_step(k);
+      if (t < N) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xsol[j][t] = myx[j];
       }
     }
     __syncthreads();
-    if (t < k) {
-      const double urk = lds[my_off + (k - t)];
+    if (w == 0) {
+#pragma unroll 1
+      for (int k = N - 1; k >= 64; --k) {
+        const double urk = lds[my_off + (k - t)];
 #pragma unroll
-      for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, xsol[j][k], bb[j]);
+        for (int j = 0; j < 3; ++j) bb[j] = __builtin_fma(-urk, xsol[j][k], bb[j]);
+      }
+#pragma unroll 1
+      for (int k = (N < 64 ? N : 64) - 1; k >= 0; --k) bsub_step(k);
     }
+  }
+  if (t < N && (WAVES == 1 || w == 0)) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) xsol[j][t] = myx[j];
   }
   __syncthreads();
 
