@@ -256,8 +256,9 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   // each batch's rank words are all in flight before its values are needed.
   double a[WC];
   if (t < n) {
-    constexpr int CB = 8;
-    static_assert(NMAX % CB == 0, "batch");
+    // two dependent global loads per batch: bigger batches where registers
+    // allow it without lowering occupancy (the two-wave kernels)
+    constexpr int CB = WAVES > 1 ? 16 : 8;
     const int my_id = S[t];
 #pragma unroll
     for (int c0 = 0; c0 < NMAX; c0 += CB) {
@@ -265,14 +266,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
       int rl[CB];
 #pragma unroll
       for (int e = 0; e < CB; ++e) {
-        const int cs = c0 + e < n ? c0 + e : 0;
-        rl[e] = my_id - rlo[cs];
-        wd[e] = rbm[rwb[cs] + (rl[e] >> 5)];
+        if (c0 + e < NMAX) {
+          const int cs = c0 + e < n ? c0 + e : 0;
+          rl[e] = my_id - rlo[cs];
+          wd[e] = rbm[rwb[cs] + (rl[e] >> 5)];
+        }
       }
 #pragma unroll
       for (int e = 0; e < CB; ++e) {
-        const int cs = c0 + e < n ? c0 + e : 0;
-        a[c0 + e] = R[rbp[cs] + (int64_t)wd[e].y + __popc(wd[e].x & ((1u << (rl[e] & 31)) - 1u))];
+        if (c0 + e < NMAX) {
+          const int cs = c0 + e < n ? c0 + e : 0;
+          a[c0 + e] = R[rbp[cs] + (int64_t)wd[e].y + __popc(wd[e].x & ((1u << (rl[e] & 31)) - 1u))];
+        }
       }
       __builtin_amdgcn_sched_barrier(0);  // keep batches apart: bounded registers in flight
     }
