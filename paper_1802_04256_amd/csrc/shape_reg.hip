@@ -159,11 +159,19 @@ __device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const d
   for (int b = 0; b < NB; ++b) {
     if (16 * b < len) {
       if (b + 1 < NB) ub[(b + 1) & 1] = u[16 * (b + 1) + c16];
+      // broadcasts four elements ahead of their multiply-adds, so a wave
+      // running alone does not wait on each DPP result in turn
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int j = 16 * b + e;
-        if (j + 1 < WC) a[j] = __builtin_fma(nl, row_bcast(ub[b & 1], e), a[j + 1]);
-        else if (j < WC) a[j] = 0.0;
+      for (int e0 = 0; e0 < 16; e0 += 4) {
+        double u4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u4[e] = row_bcast(ub[b & 1], e0 + e);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 16 * b + e0 + e;
+          if (j + 1 < WC) a[j] = __builtin_fma(nl, u4[e], a[j + 1]);
+          else if (j < WC) a[j] = 0.0;
+        }
       }
     }
   }
@@ -380,8 +388,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
       // (the pivot's window is already stored as its U row)
       const bool upd = real && pos > k;
       const double l = upd ? a[0] / urow[0] : 0.0;
-      if (keep && upd) Lkeep[(int64_t)k * N + t] = l;
       shift_update<NB, WC>(a, -l, urow + 1, len, lane & 15);
+      if (keep && upd) Lkeep[(int64_t)k * N + t] = l;  // after the update: no branch between the two
     }
     uoff += (len + 1) & ~1;
   }
