@@ -19,17 +19,18 @@
 //           (With one wave per point both barriers are unnecessary: a wave's
 //           LDS accesses complete in program order.)
 // Back substitution then runs by position from the U rows in LDS, k
-// descending: x_k = b_k / u_kk, b_r = fma(-u_rk, x_k, b_r) for r < k.
+// descending: x_k = b_k / u_kk, b_r = fma(-u_rk, x_k, b_r) for r < k; x_k
+// reaches the other threads of its wave by readlane.
 //
 // Every register index is static: element 0 is always the pivot column.  The
 // winner's write and the update walk the window in blocks of sixteen columns,
 // skipping blocks past the row's end under uniform branches.  The pivot row
 // reaches the other rows one element per lane from LDS and is spread across
-// each row of sixteen lanes by DPP broadcasts.  LDS instructions are the
-// scarce resource of this kernel (each one holds the CU's LDS pipe for about
-// the same time however few lanes it serves, and eight waves share it), so a
-// step issues one candidate write, one winner write per two columns, and per
-// wave one read per sixteen columns.  Code size is O(NMAX).
+// each row of sixteen lanes by DPP broadcasts.  A workgroup's time is the
+// latency of its chain of N steps (pivot search, exchange, row write,
+// division, update): a workgroup alone on a CU takes as long per step as one
+// among a full load, so the step is kept short rather than lean, and
+// throughput comes from the points resident per CU.  Code size is O(NMAX).
 #include <cfloat>
 #include <climits>
 
