@@ -116,3 +116,25 @@ def test_backward_needs_kept_factors():
     with pytest.raises(rp.RpimError) as ei:
         plan.assemble_backward(prob.node_xyz, prob.cell_E, prob.nu, np.zeros(plan.nnz))
     assert ei.value.code == -8
+
+
+def test_backward_large_supports(oracle_mod):
+    # supports up to 131 rows: the adjoint's per-point kernel runs two and three
+    # waves, handing substitution values between waves through LDS
+    import paper_1802_04256_amd as rp
+    prob = W.box(n=8, p=2, jitter=0.3, jitter_seed=61, E_seed=62)
+    prob.support_radius = 3.05
+    print(f"[gpu case] adjoint box8 radius 3.05: nodes={prob.n_nodes} gps={prob.n_gp}", flush=True)
+    m = oracle_mod.OracleModel(prob)
+    m.build_pattern()
+    plan = rp.Plan.from_problem(prob)
+    plan.build_pattern()
+    assert plan.info()["max_n"] + 4 > 128
+    row_ptr, col_idx = m.pattern()
+    Kb = probe_kbar(row_ptr, col_idx, 3 * prob.n_nodes)
+    plan.assemble(cell_E=prob.cell_E, nu=prob.nu, keep_factors=True)
+    dE, dX = plan.assemble_backward(prob.node_xyz, prob.cell_E, prob.nu, Kb)
+    plan.status()
+    dEo, dXo = m.backward(Kb)
+    assert rel_err(dE.cpu().numpy(), dEo) < 1e-10
+    assert rel_err(dX.cpu().numpy(), dXo) < 1e-6
