@@ -365,27 +365,43 @@ def test_timoshenko_refined_closer(oracle_mod, cant):
 # --------------------------------------------------------------------------
 # penalty boundary conditions (stage 2)
 # --------------------------------------------------------------------------
+def _read_golden(name):
+    """Parse a tests/golden fixture: '#' comments, a 'matrix' block, then 'key values...' lines."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows, fields, in_matrix = [], {}, False
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        if line == "matrix":
+            in_matrix = True
+            continue
+        head = line.split()[0]
+        if in_matrix and not head[0].isalpha():
+            rows.append([float(v) for v in line.split()])
+            continue
+        in_matrix = False
+        fields[head] = [float(v) for v in line.split()[1:]]
+    return np.array(rows), fields
+
+
 def test_penalty_hand_computed(oracle_mod):
-    # 6x6 symmetric CSR with a full tridiagonal + corner pattern
-    Kd = np.array([[4, 1, 0, 0, 0, 2],
-                   [1, 5, 1, 0, 0, 0],
-                   [0, 1, 9, 1, 0, 0],
-                   [0, 0, 1, 3, 1, 0],
-                   [0, 0, 0, 1, 7, 1],
-                   [2, 0, 0, 0, 1, 6]], float)
+    # 6x6 symmetric CSR with a full tridiagonal + corner pattern; expected values
+    # are hand-computed from the definition (tests/golden/penalty_6x6.txt)
+    Kd, f = _read_golden("penalty_6x6.txt")
     S = sp.csr_matrix(Kd)
     S.sort_indices()
     rp, ci = S.indptr.astype(np.int64), S.indices.astype(np.int32)
     K = S.data.copy()
     rhs = np.zeros(6)
-    alpha = oracle_mod.penalty(rp, ci, K, np.array([1, 4], np.int32), u_bar=np.array([0.5, -2.0]),
-                               factor=10.0, rhs=rhs)
-    assert alpha == 90.0
+    dofs = np.array(f["constrained"], np.int32)
+    alpha = oracle_mod.penalty(rp, ci, K, dofs, u_bar=np.array(f["u_bar"]), factor=f["factor"][0], rhs=rhs)
+    assert alpha == f["alpha"][0]
     expect = Kd.copy()
-    expect[1, 1] += 90.0
-    expect[4, 4] += 90.0
+    np.fill_diagonal(expect, f["diag_after"])
     assert np.array_equal(sp.csr_matrix((K, ci, rp), shape=(6, 6)).toarray(), expect)
-    assert np.array_equal(rhs, np.array([0, 45.0, 0, 0, -180.0, 0]))
+    assert np.array_equal(rhs, np.array(f["rhs_after"]))
     with pytest.raises(oracle_mod.OracleError):
         oracle_mod.penalty(rp, ci, K, np.array([2, 2], np.int32), factor=10.0)
 
