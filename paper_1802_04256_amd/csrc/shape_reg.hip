@@ -217,15 +217,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_win(
   __shared__ Cand cand[2][WAVES];
   __shared__ int uoffs[NMAX];                 // start of U row k in lds
   __shared__ double xsol[3][NMAX];
-  __shared__ int S[NMAX];
-  __shared__ int rlo[NMAX];          // per support node: first id of its row window,
-  __shared__ int64_t rwb[NMAX];      // its rank-bitmap word offset,
-  __shared__ int64_t rbp[NMAX];      // and its pattern row start
-  __shared__ double xs[3 * NMAX];    // support node coordinates
   __shared__ int rowat[NMAX];
   __shared__ double xg[3];
   __shared__ double rmax[WAVES];
-  __shared__ double coefs[NMAX];
+  // Per-support-node data of the build phase share the U storage: every read
+  // of them comes before the barrier that ends the build, and U is written
+  // only after it.  The smaller footprint lets more points reside per CU,
+  // which is what the latency-bound elimination needs.
+  static_assert(7 * NMAX <= US, "build data fit in the U storage");
+  double* const xs = lds;                                          // [3 NMAX] support node coordinates
+  double* const coefs = lds + 3 * NMAX;                            // [NMAX] right-hand-side coefficients
+  int64_t* const rwb = reinterpret_cast<int64_t*>(lds + 4 * NMAX);  // [NMAX] rank-bitmap word offset of the row,
+  int64_t* const rbp = reinterpret_cast<int64_t*>(lds + 5 * NMAX);  // [NMAX] and its pattern row start
+  int* const S = reinterpret_cast<int*>(lds + 6 * NMAX);            // [NMAX] support node ids
+  int* const rlo = S + NMAX;                                       // [NMAX] first id of each node's row window
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t g = gp_order[order_begin + blockIdx.x];
