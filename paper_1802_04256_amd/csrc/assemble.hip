@@ -333,7 +333,11 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
         for (int be = 0; be < 3; ++be) {
           double m2 = m[be][al];  // phi_I,beta * phi_J,alpha
           if (al == be) m2 = m2 + dot;
-          a[3 * al + be] = a[3 * al + be] + __builtin_fma(lc, m[al][be], mc * m2);
+          // LDS FP64 add (ds_add_f64): no read round trip; a wave's LDS
+          // operations execute in program order and no two lanes or waves
+          // share a slot, so each slot still sums in ascending g
+          __hip_atomic_fetch_add(a + 3 * al + be, __builtin_fma(lc, m[al][be], mc * m2), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     } else {
       const float flc = (float)lc, fmc = (float)mc;
