@@ -58,7 +58,7 @@ typedef enum {
 typedef enum {
   RPIM_FP64 = 0,  /* K is double[nnz]; everything FP64                         */
   RPIM_MIXED = 1  /* K is float[nnz]: FP64 moment matrix + LU, FP32 B^T D B,
-                     FP32 Kahan-compensated accumulation                       */
+                     each entry summed in FP64, rounded once to FP32           */
 } rpim_precision;
 
 /* One model, or a block-diagonal batch of independent models.

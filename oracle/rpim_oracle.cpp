@@ -44,7 +44,8 @@
 //   C9  every K entry is +0 + e_g1 + e_g2 + ... in ascending Gauss-point id.
 //   C10 no other contraction (built with -ffp-contract=off).
 //   C11 mixed precision: FP64 up to dphi; dphi, lc, mc rounded to float; C8 in
-//       float; per-entry Kahan sum in float in ascending g.
+//       float; each entry sums its float terms in double in ascending g
+//       (from +0) and is rounded to float once at the end.
 //
 // An extended-precision (__float128) evaluation of the same formulas, with the
 // supports frozen, backs the finite-difference gradient checks.
@@ -396,9 +397,9 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
   const int64_t nnz = (int64_t)col_idx.size();
   double* K64 = (double*)K_vals;
   float* K32 = (float*)K_vals;
-  std::vector<float> comp;  // Kahan compensation (C11)
+  std::vector<double> acc;  // C11: per-entry double sums of the float terms
   if (precision == 0) std::fill(K64, K64 + nnz, 0.0);
-  else { std::fill(K32, K32 + nnz, 0.0f); comp.assign(nnz, 0.0f); }
+  else acc.assign(nnz, 0.0);
   double lam, mu;
   lame_hat(nu, &lam, &mu);
   const int64_t count = gps ? n_gps : m.G;
@@ -436,15 +437,14 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
               float m2 = fa[be] * fb[al];
               if (al == be) m2 = m2 + dot;
               float e = std::fmaf(flc, m1, fmc * m2);
-              float y = e - comp[pos];
-              float t = K32[pos] + y;
-              comp[pos] = (t - K32[pos]) - y;
-              K32[pos] = t;
+              acc[pos] = acc[pos] + (double)e;
             }
           }
       }
     }
   }
+  if (precision == 1)
+    for (int64_t p = 0; p < nnz; ++p) K32[p] = (float)acc[p];
   return OK;
 }
 

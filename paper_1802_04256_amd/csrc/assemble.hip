@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* acc = smem;                 // [L][9] FP64, or [L][9] float2 (sum, compensation)
+  double* acc = smem;                 // [L][9] double sums (both precisions)
   uint2* bm = (uint2*)(acc + 9 * L);  // row I's rank bitmap
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
       for (int al = 0; al < 3; ++al)
 #pragma unroll
         for (int be = 0; be < 3; ++be) m[al][be] = pI[al] * pJ[be];
-      float2* a = reinterpret_cast<float2*>(acc) + 9 * pos;
+      double* a = acc + 9 * pos;
 #pragma unroll
       for (int al = 0; al < 3; ++al)
 #pragma unroll
@@ -355,12 +355,8 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
           float m2 = m[be][al];
           if (al == be) m2 = m2 + dot;
           const float ev = __builtin_fmaf(flc, m[al][be], fmc * m2);
-          float2 sc = a[3 * al + be];  // Kahan: (sum, compensation)
-          const float y = ev - sc.y;
-          const float t = sc.x + y;
-          sc.y = (t - sc.x) - y;
-          sc.x = t;
-          a[3 * al + be] = sc;
+          // the float term joins the slot's double sum (ds_add_f64, in ascending g)
+          __hip_atomic_fetch_add(a + 3 * al + be, (double)ev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
   };
@@ -400,7 +396,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
     const int pos = idx / 9, r = idx - 9 * pos, a = r / 3, be = r - 3 * a;
     const int64_t o = base + 3 * (int64_t)a * L + 3 * pos + be;
     if (!kMixed) ((double*)Kout)[o] = acc[idx];
-    else ((float*)Kout)[o] = reinterpret_cast<float2*>(acc)[idx].x;
+    else ((float*)Kout)[o] = (float)acc[idx];  // one rounding of the double sum
   }
 }
 
