@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # the kernel sources it was measured on: any change to them reports traffic as null until re-measured.
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "66ee5fad1be8beac2ecc2550ee6573bc1a02303b03908f226ab0ad4142f072fe", "bytes_per_step": 3.914e10}
+SHAPE_TRAFFIC = {"sources_sha256": "3435088aed439cc687bcaa354b31fb55def2520986f3e2db743ebe84b55c24cb", "bytes_per_step": 3.903e10}
 
 
 def log(*a):
