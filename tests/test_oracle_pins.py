@@ -409,6 +409,57 @@ def test_penalty_hand_computed(oracle_mod):
 # --------------------------------------------------------------------------
 # mixed precision (contract C11) against FP64
 # --------------------------------------------------------------------------
+def test_mixed_is_float_terms_summed_in_double(cant):
+    """The mixed path's definition, rebuilt in numpy from the FP64 gradients:
+    each point's block term in float32 (products rounded to float, the two
+    fused multiply-adds of the contract evaluated exactly in double and
+    rounded once), each entry the double sum of its terms in ascending point
+    order, rounded to float32 once.  Within one float32 ulp of the oracle
+    (double rounding of the emulated fused adds is the only difference),
+    while summing the same terms in float32 misses by more somewhere."""
+    p, m = cant
+    gp_ptr, gp_nbr = m.support()
+    row_ptr, col_idx = m.pattern()
+    gps = np.arange(40, dtype=np.int64)  # neighbouring points: entries collect many terms
+    lam = p.nu / ((1 + p.nu) * (1 - 2 * p.nu))
+    mu = 1 / (2 * (1 + p.nu))
+    f32 = np.float32
+    acc, acc32 = {}, {}  # double sums (the definition) and float sums (a wrong model)
+    for g in gps:
+        S = gp_nbr[gp_ptr[g]:gp_ptr[g + 1]]
+        _, dphi = m.shape(int(g))
+        fp = dphi.astype(f32)
+        c = p.gp_wdet[g] * p.cell_E[p.gp_cell[g]]
+        flc, fmc = f32(c * lam), f32(c * mu)
+        for a in range(len(S)):
+            for b in range(len(S)):
+                fa, fb = fp[a], fp[b]
+                dot = f32(float(fa[2]) * float(fb[2]) + float(f32(float(fa[1]) * float(fb[1]) + float(f32(fa[0] * fb[0])))))
+                for al in range(3):
+                    for be in range(3):
+                        m1 = f32(fa[al] * fb[be])
+                        m2 = f32(fa[be] * fb[al])
+                        if al == be:
+                            m2 = f32(m2 + dot)
+                        e = f32(float(flc) * float(m1) + float(f32(fmc * m2)))
+                        key = (3 * S[a] + al, 3 * S[b] + be)
+                        acc[key] = acc.get(key, 0.0) + float(e)
+                        acc32[key] = f32(acc32.get(key, f32(0.0)) + e)
+    K32 = m.assemble(precision=1, gps=gps)
+    for (r, cidx), v in acc.items():
+        pos = row_ptr[r] + np.searchsorted(col_idx[row_ptr[r]:row_ptr[r + 1]], cidx)
+        want = f32(v)
+        assert abs(float(K32[pos]) - float(want)) <= float(np.spacing(abs(want))), (r, cidx)
+    # entries outside these points' blocks stay zero
+    assert np.count_nonzero(K32) <= len(acc)
+    # the check can tell the definition from float accumulation
+    miss = 0
+    for (r, cidx), v in acc32.items():
+        pos = row_ptr[r] + np.searchsorted(col_idx[row_ptr[r]:row_ptr[r + 1]], cidx)
+        miss += abs(float(K32[pos]) - float(v)) > float(np.spacing(abs(v)))
+    assert miss > 0
+
+
 @pytest.mark.parametrize("which", ["cant", "jbox"])
 def test_mixed_within_1e6(which, request):
     p, m = request.getfixturevalue(which)
