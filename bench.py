@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # the kernel sources it was measured on: any change to them reports traffic as null until re-measured.
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "3435088aed439cc687bcaa354b31fb55def2520986f3e2db743ebe84b55c24cb", "bytes_per_step": 3.903e10}
+SHAPE_TRAFFIC = {"sources_sha256": "3cdd9b187e9f4577b3e909845dd5c40721d78f462ff639176c2fc55c40b49cd8", "bytes_per_step": 3.903e10}
 
 
 def log(*a):

@@ -56,15 +56,6 @@ __global__ void k_pow_test(const double* x, double q, double* y, int64_t n, DevS
   if (hard && st) flag_error(st, kFlagPow, -1);
 }
 
-// First index of `key` in the sorted range [b, e) (the caller guarantees presence).
-__device__ __forceinline__ int64_t find_sorted(const int32_t* v, int64_t b, int64_t e, int32_t key) {
-  while (b < e) {
-    const int64_t m = (b + e) >> 1;
-    if (v[m] < key) b = m + 1; else e = m;
-  }
-  return b;
-}
-
 // Block-wide argmax of (value, row) with ties to the smaller row.
 __device__ __forceinline__ void argmax_pair(double v, int r, double* sv, int* sr, double* out_v, int* out_r) {
   for (int o = 32; o > 0; o >>= 1) {

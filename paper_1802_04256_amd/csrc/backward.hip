@@ -43,14 +43,6 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ int64_t find_sorted(const int32_t* v, int64_t b, int64_t e, int32_t key) {
-  while (b < e) {
-    const int64_t m = (b + e) >> 1;
-    if (v[m] < key) b = m + 1; else e = m;
-  }
-  return b;
-}
-
 // M = Kbar + Kbar^T, stored on the scalar CSR layout of K.
 __global__ void k_symmetrize(int64_t nblk, const int64_t* blk_ptr, const int32_t* blk_row, const int32_t* blk_col,
                              const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* dK,
