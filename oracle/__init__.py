@@ -48,7 +48,7 @@ def lib():
         L.orcl_shape.argtypes = [vp, i64, dp, dp, dp]
         L.orcl_assemble.argtypes = [vp, dp, dp, d, C.c_int, vp, i64p, i64, i64p]
         L.orcl_penalty.argtypes = [i64p, i32p, vp, C.c_int, i64, i32p, dp, i64, d, dp, dp]
-        L.orcl_assemble_backward.argtypes = [vp, dp, dp, d, dp, dp, dp]
+        L.orcl_assemble_backward.argtypes = [vp, dp, dp, d, dp, i64p, i64, dp, dp]
         L.orcl_dot_q.argtypes = [vp, dp, dp, d, dp, i64p, i64, dp]
         L.orcl_pow_cr.restype = d
         L.orcl_pow_cr.argtypes = [d, d]
@@ -144,14 +144,17 @@ class OracleModel:
             raise OracleError(st, f"assemble (first bad gp {bad.value})")
         return K
 
-    def backward(self, Kbar, cell_E=None, nu=None, node_xyz=None):
+    def backward(self, Kbar, cell_E=None, nu=None, node_xyz=None, gps=None):
+        """dL/dE per cell and dL/dx per node, summed over `gps` (ascending; all points when None)."""
         E = np.ascontiguousarray(self.prob.cell_E if cell_E is None else cell_E, np.float64)
         X = None if node_xyz is None else np.ascontiguousarray(node_xyz, np.float64)
         Kb = np.ascontiguousarray(Kbar, np.float64)
+        g = None if gps is None else np.ascontiguousarray(gps, np.int64)
         dE = np.empty(self.prob.n_cells)
         dX = np.empty((self.prob.n_nodes, 3))
         _check(lib().orcl_assemble_backward(self.h, _p(X), _p(E), self.prob.nu if nu is None else nu,
-                                            _p(Kb), _p(dE), _p(dX)), "assemble_backward")
+                                            _p(Kb), _p(g), 0 if g is None else len(g), _p(dE), _p(dX)),
+               "assemble_backward")
         return dE, dX
 
     def dot_q(self, Kbar, gps, node_xyz=None, cell_E=None, nu=None):

@@ -5,10 +5,10 @@
 // CPU-baseline leg may load it; the product path never does.  It shares no
 // code, header, table or constant with the GPU library.
 //
-// What it computes (paper: GeoMFree3D, Sec. 2 "three major stages" and the
-// RPIM of Liu cited in Sec. 1; the paper prints no equations, so the method is
-// the standard polynomial-augmented radial point interpolation in its Galerkin
-// form for 3D linear elasticity):
+// What it computes (GeoMFree3D Sec. 2: stage 1 assembly, stage 2 penalty
+// boundary conditions; the method is the RPIM of Liu cited in Sec. 1, and the
+// paper prints no equations, so it is the standard polynomial-augmented radial
+// point interpolation in its Galerkin form for 3D linear elasticity):
 //
 //   K = sum_g  w_g |J_g| E_c(g)  B_g^T  D(E=1, nu)  B_g            (stage 1)
 //
@@ -43,9 +43,11 @@
 //       mu = 1/(2(1+nu)).
 //   C9  every K entry is +0 + e_g1 + e_g2 + ... in ascending Gauss-point id.
 //   C10 no other contraction (built with -ffp-contract=off).
-//   C11 mixed precision: FP64 up to dphi; dphi, lc, mc rounded to float; C8 in
-//       float; each entry sums its float terms in double in ascending g
-//       (from +0) and is rounded to float once at the end.
+//   C11 mixed precision: FP64 up to dphi (moment matrix and LU stay FP64);
+//       dphi, lc, mc rounded to float; C8 evaluated in float (fmaf); each
+//       entry is a compensated (Kahan) float sum of its terms in ascending g:
+//       s = c = +0; per term e: y = e - c, t = s + y, c = (t - s) - y, s = t;
+//       the entry is s.
 //
 // An extended-precision (__float128) evaluation of the same formulas, with the
 // supports frozen, backs the finite-difference gradient checks.
@@ -382,7 +384,8 @@ int orcl_shape(void* h, int64_t g, const double* node_xyz, double* phi, double* 
 }
 
 // Stage 1: K over the listed Gauss points (all when gps == NULL), ascending g.
-// precision 0: K is double[nnz] (C8, C9).  precision 1: K is float[nnz] (C11).
+// precision 0: K is double[nnz] (C8, C9).  precision 1: K is float[nnz], the
+// compensated float sums of C11.
 int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double nu, int precision,
                   void* K_vals, const int64_t* gps, int64_t n_gps, int64_t* first_bad_gp) {
   Model& m = *(Model*)h;
@@ -397,9 +400,12 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
   const int64_t nnz = (int64_t)col_idx.size();
   double* K64 = (double*)K_vals;
   float* K32 = (float*)K_vals;
-  std::vector<double> acc;  // C11: per-entry double sums of the float terms
+  std::vector<float> kc;  // C11: Kahan compensation per entry (the running sum is K32 itself)
   if (precision == 0) std::fill(K64, K64 + nnz, 0.0);
-  else acc.assign(nnz, 0.0);
+  else {
+    std::fill(K32, K32 + nnz, 0.0f);
+    kc.assign(nnz, 0.0f);
+  }
   double lam, mu;
   lame_hat(nu, &lam, &mu);
   const int64_t count = gps ? n_gps : m.G;
@@ -437,14 +443,17 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
               float m2 = fa[be] * fb[al];
               if (al == be) m2 = m2 + dot;
               float e = std::fmaf(flc, m1, fmc * m2);
-              acc[pos] = acc[pos] + (double)e;
+              // compensated float sum (Kahan): the compensation carries the
+              // low-order part lost when e joins the running sum
+              float y = e - kc[pos];
+              float t = K32[pos] + y;
+              kc[pos] = (t - K32[pos]) - y;
+              K32[pos] = t;
             }
           }
       }
     }
   }
-  if (precision == 1)
-    for (int64_t p = 0; p < nnz; ++p) K32[p] = (float)acc[p];
   return OK;
 }
 
@@ -483,9 +492,12 @@ int orcl_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, i
 // Per Gauss point: Phibar = dL_g/dphi; lambda_k = G^{-T} [Phibar_k; 0]
 // (G is symmetric, so its own LU serves); Gbar = -sum_k lambda_k gamma_k^T;
 // then the chain rule through R(s_ab), the polynomial block and the
-// derivative right-hand sides.  Accumulated in ascending g.
+// derivative right-hand sides.  Accumulated in ascending g over the listed
+// Gauss points (all when gps == NULL): a node's or a cell's value is complete
+// when every Gauss point whose support holds the node, or that lies in the
+// cell, is listed.
 int orcl_assemble_backward(void* h, const double* node_xyz, const double* cell_E, double nu,
-                           const double* Kbar, double* dE, double* dX) {
+                           const double* Kbar, const int64_t* gps, int64_t n_gps, double* dE, double* dX) {
   Model& m = *(Model*)h;
   if (!m.built) return E_STATE;
   const double* X = node_xyz ? node_xyz : m.node.data();
@@ -501,7 +513,10 @@ int orcl_assemble_backward(void* h, const double* node_xyz, const double* cell_E
   const double q = m.q;
   std::vector<double> sol, lu;
   std::vector<int> piv;
-  for (int64_t g = 0; g < m.G; ++g) {
+  const int64_t count = gps ? n_gps : m.G;
+  for (int64_t it = 0; it < count; ++it) {
+    const int64_t g = gps ? gps[it] : it;
+    if (g < 0 || g >= m.G) return E_ARG;
     int st = gp_solve<double>(m, X, g, 3, sol, &lu, &piv);
     if (st != OK) return st;
     const int64_t b0 = m.gp_ptr[g];

@@ -409,55 +409,131 @@ def test_penalty_hand_computed(oracle_mod):
 # --------------------------------------------------------------------------
 # mixed precision (contract C11) against FP64
 # --------------------------------------------------------------------------
-def test_mixed_is_float_terms_summed_in_double(cant):
-    """The mixed path's definition, rebuilt in numpy from the FP64 gradients:
-    each point's block term in float32 (products rounded to float, the two
-    fused multiply-adds of the contract evaluated exactly in double and
-    rounded once), each entry the double sum of its terms in ascending point
-    order, rounded to float32 once.  Within one float32 ulp of the oracle
-    (double rounding of the emulated fused adds is the only difference),
-    while summing the same terms in float32 misses by more somewhere."""
-    p, m = cant
+def fmaf_exact(a, b, c):
+    """Correctly rounded float32 a*b + c (round to nearest even) for normal float32 arrays.
+
+    a*b is exact in double; s = fl64(a*b + c) and its exact error err come from
+    Knuth's TwoSum, so a*b + c = s + err exactly.  Rounding s to float32 is the
+    correctly rounded result unless s sits exactly on a midpoint between two
+    float32 values while err != 0; then the exact value lies on err's side."""
+    f32, f64 = np.float32, np.float64
+    p = a.astype(f64) * b.astype(f64)
+    c64 = c.astype(f64)
+    s = p + c64
+    bb = s - p
+    err = (p - (s - bb)) + (c64 - bb)
+    r = s.astype(f32)
+    r64 = r.astype(f64)
+    other = np.nextafter(r, np.where(s > r64, np.inf, -np.inf).astype(f32))
+    mid = 0.5 * (r64 + other.astype(f64))
+    at_mid = (s == mid) & (err != 0)
+    hi, lo = np.maximum(r, other), np.minimum(r, other)
+    return np.where(at_mid, np.where(err > 0, hi, lo), r).astype(f32)
+
+
+def test_fmaf_exact_emulation():
+    # the helper against the exact rational value on random operands, including
+    # constructed midpoint cases where a plain double evaluation rounds twice
+    from fractions import Fraction
+    rng = np.random.default_rng(17)
+    f32 = np.float32
+    a = rng.standard_normal(3000).astype(f32)
+    b = rng.standard_normal(3000).astype(f32)
+    c = rng.standard_normal(3000).astype(f32)
+    # midpoint cases: a*b = 1 + (k+1) 2^-12 + k 2^-24 lies exactly halfway between two
+    # float32 values for odd k; c = +-2^-60 moves the exact sum off the midpoint by far
+    # less than half a double ulp, so a double evaluation rounds onto it and then ties
+    k = np.arange(1, 200, 2, dtype=np.float64)
+    a2 = (1.0 + k * 2.0 ** -12).astype(f32)
+    b2 = np.full(len(k), f32(1.0 + 2.0 ** -12))
+    c2 = np.where(np.arange(len(k)) % 2 == 0, 2.0 ** -60, -(2.0 ** -60)).astype(f32)
+    a, b, c = np.concatenate([a, a2]), np.concatenate([b, b2]), np.concatenate([c, c2])
+    got = fmaf_exact(a, b, c)
+
+    def rn32(x):
+        # nearest float32 to the rational x, ties to even
+        lo = f32(float(x))
+        cands = {lo, np.nextafter(lo, f32(np.inf)), np.nextafter(lo, f32(-np.inf))}
+        best = sorted(cands, key=lambda v: (abs(Fraction(float(v)) - x), int(np.float32(v).view(np.int32)) & 1))
+        return best[0]
+    twice = 0
+    for i in range(len(a)):
+        exact = Fraction(float(a[i])) * Fraction(float(b[i])) + Fraction(float(c[i]))
+        assert got[i] == rn32(exact), i
+        twice += f32(float(a[i]) * float(b[i]) + float(c[i])) != got[i]
+    assert twice > 0  # the naive double evaluation is wrong somewhere: the test can tell
+
+
+def _mixed_models(p, m, gps):
+    """Per entry, from the oracle's FP64 gradients: the C11 terms (float32, fmaf) summed
+    (a) by the compensated float sum of C11, (b) in double and rounded once, (c) in float."""
     gp_ptr, gp_nbr = m.support()
     row_ptr, col_idx = m.pattern()
-    gps = np.arange(40, dtype=np.int64)  # neighbouring points: entries collect many terms
+    ndof = len(row_ptr) - 1
+    pos_of = -np.ones((ndof, ndof), np.int64)  # small models only
+    rows = np.repeat(np.arange(ndof), np.diff(row_ptr))
+    pos_of[rows, col_idx] = np.arange(len(col_idx))
     lam = p.nu / ((1 + p.nu) * (1 - 2 * p.nu))
     mu = 1 / (2 * (1 + p.nu))
     f32 = np.float32
-    acc, acc32 = {}, {}  # double sums (the definition) and float sums (a wrong model)
+    nnz = len(col_idx)
+    ks, kc = np.zeros(nnz, f32), np.zeros(nnz, f32)
+    dsum = np.zeros(nnz, np.float64)
+    asum = np.zeros(nnz, np.float64)
+    fsum = np.zeros(nnz, f32)
     for g in gps:
         S = gp_nbr[gp_ptr[g]:gp_ptr[g + 1]]
+        n = len(S)
         _, dphi = m.shape(int(g))
         fp = dphi.astype(f32)
         c = p.gp_wdet[g] * p.cell_E[p.gp_cell[g]]
         flc, fmc = f32(c * lam), f32(c * mu)
-        for a in range(len(S)):
-            for b in range(len(S)):
-                fa, fb = fp[a], fp[b]
-                dot = f32(float(fa[2]) * float(fb[2]) + float(f32(float(fa[1]) * float(fb[1]) + float(f32(fa[0] * fb[0])))))
-                for al in range(3):
-                    for be in range(3):
-                        m1 = f32(fa[al] * fb[be])
-                        m2 = f32(fa[be] * fb[al])
-                        if al == be:
-                            m2 = f32(m2 + dot)
-                        e = f32(float(flc) * float(m1) + float(f32(fmc * m2)))
-                        key = (3 * S[a] + al, 3 * S[b] + be)
-                        acc[key] = acc.get(key, 0.0) + float(e)
-                        acc32[key] = f32(acc32.get(key, f32(0.0)) + e)
+        A = np.repeat(np.arange(n), n)
+        B = np.tile(np.arange(n), n)
+        fa, fb = fp[A], fp[B]
+        dot = fmaf_exact(fa[:, 2], fb[:, 2], fmaf_exact(fa[:, 1], fb[:, 1], fa[:, 0] * fb[:, 0]))
+        for al in range(3):
+            for be in range(3):
+                m1 = fa[:, al] * fb[:, be]
+                m2 = fa[:, be] * fb[:, al]
+                if al == be:
+                    m2 = m2 + dot
+                e = fmaf_exact(np.full(len(A), flc), m1, fmc * m2)
+                pos = pos_of[3 * S[A] + al, 3 * S[B] + be]
+                assert (pos >= 0).all()
+                y = e - kc[pos]
+                t = ks[pos] + y
+                kc[pos] = (t - ks[pos]) - y
+                ks[pos] = t
+                dsum[pos] += e.astype(np.float64)
+                asum[pos] += np.abs(e.astype(np.float64))
+                fsum[pos] = fsum[pos] + e
+    return ks, dsum, asum, fsum
+
+
+def test_mixed_is_compensated_float_sum(cant):
+    """C11 rebuilt in numpy from the oracle's FP64 gradients: float32 terms
+    (fused multiply-adds emulated exactly), each entry a Kahan-compensated
+    float32 sum in ascending point order.  The oracle's mixed K equals it bit
+    for bit, and the check tells it apart from summing the same terms in
+    double (rounded once) and from a plain float32 sum."""
+    p, m = cant
+    gps = np.arange(p.n_gp, dtype=np.int64)
+    kahan, dsum, asum, flt = _mixed_models(p, m, gps)
     K32 = m.assemble(precision=1, gps=gps)
-    for (r, cidx), v in acc.items():
-        pos = row_ptr[r] + np.searchsorted(col_idx[row_ptr[r]:row_ptr[r + 1]], cidx)
-        want = f32(v)
-        assert abs(float(K32[pos]) - float(want)) <= float(np.spacing(abs(want))), (r, cidx)
-    # entries outside these points' blocks stay zero
-    assert np.count_nonzero(K32) <= len(acc)
-    # the check can tell the definition from float accumulation
-    miss = 0
-    for (r, cidx), v in acc32.items():
-        pos = row_ptr[r] + np.searchsorted(col_idx[row_ptr[r]:row_ptr[r + 1]], cidx)
-        miss += abs(float(K32[pos]) - float(v)) > float(np.spacing(abs(v)))
-    assert miss > 0
+    assert K32.dtype == np.float32
+    assert np.array_equal(K32, kahan)
+    assert np.count_nonzero(K32 != dsum.astype(np.float32)) > 0
+    assert np.count_nonzero(K32 != flt) > 0
+    # compensated summation error bound: |s - sum e| <= (2u + O(n u^2)) sum |e|, u = 2^-24
+    # (the double sum of the same float terms is exact to ~1e-16 sum |e|)
+    u = 2.0 ** -24
+    n_terms = 2 * 27
+    assert np.all(np.abs(K32.astype(np.float64) - dsum) <= (2 * u + n_terms * u * u) * asum + 1e-300)
+    # and a plain float32 sum of the same terms breaks that bound somewhere
+    assert np.any(np.abs(flt.astype(np.float64) - dsum) > (2 * u + n_terms * u * u) * asum)
+    K64 = m.assemble(gps=gps)
+    assert np.linalg.norm(K32 - K64) / np.linalg.norm(K64) < 1e-6
 
 
 @pytest.mark.parametrize("which", ["cant", "jbox"])
@@ -468,3 +544,71 @@ def test_mixed_within_1e6(which, request):
     err = np.linalg.norm(K32.astype(np.float64) - K64) / np.linalg.norm(K64)
     assert err < 1e-6
     assert err > 0
+
+
+# --------------------------------------------------------------------------
+# singular moment matrices (contract C6: |u_kk| <= N eps max|G| is an error)
+# --------------------------------------------------------------------------
+def test_coplanar_support_is_singular_at_first_such_point(oracle_mod):
+    """A 3D block of nodes plus a planar sheet far from it.  Gauss points in
+    the block have full 3D supports; a Gauss point in the sheet's plane sees
+    only coplanar nodes, so the z column of its polynomial block is exactly
+    zero and elimination reaches an exactly zero pivot.  The first such point
+    (id fixed by construction) is the one reported."""
+    g3 = np.stack(np.meshgrid(*(np.arange(5.0),) * 3, indexing="ij"), -1).reshape(-1, 3)
+    sx, sy = np.meshgrid(np.arange(6.0), np.arange(6.0), indexing="ij")
+    sheet = np.stack([sx.ravel() + 40.0, sy.ravel(), np.full(36, 50.0)], 1)
+    nodes = np.concatenate([g3, sheet])
+    rng = np.random.default_rng(4)
+    block_gps = 1.0 + 2.0 * rng.random((7, 3))
+    sheet_gps = np.stack([42.0 + rng.random(3), 2.0 + rng.random(3), np.full(3, 50.0)], 1)
+    gps = np.concatenate([block_gps, sheet_gps, block_gps[:2] + 0.1])
+    first_bad = len(block_gps)
+    p = W.Problem(name="coplanar", node_xyz=nodes, gp_xyz=gps, gp_wdet=np.ones(len(gps)),
+                  gp_cell=np.zeros(len(gps), np.int32), cell_E=np.ones(1), support_radius=2.5)
+    m = oracle_mod.OracleModel(p)
+    m.build_pattern()
+    gp_ptr, gp_nbr = m.support()
+    for g in range(first_bad, first_bad + 3):  # the construction: sheet points see only the sheet
+        S = gp_nbr[gp_ptr[g]:gp_ptr[g + 1]]
+        assert len(S) >= 5 and np.all(nodes[S, 2] == 50.0)
+    with pytest.raises(oracle_mod.OracleError) as ei:
+        m.assemble()
+    assert ei.value.code == oracle_mod.E_SINGULAR
+    assert f"first bad gp {first_bad})" in str(ei.value)
+    with pytest.raises(oracle_mod.OracleError) as ei:
+        m.shape(first_bad + 1)
+    assert ei.value.code == oracle_mod.E_SINGULAR
+    # every point before it, and the block points after it, are regular
+    ok = np.r_[np.arange(first_bad), np.arange(first_bad + 3, len(gps))]
+    K = m.assemble(gps=ok)
+    assert np.isfinite(K).all() and np.abs(K).max() > 0
+
+
+# --------------------------------------------------------------------------
+# adjoint over a subset of Gauss points
+# --------------------------------------------------------------------------
+def test_backward_subset_completes_touched_nodes_and_cells(jbox, oracle_mod):
+    """The backward over the Gauss points that touch a node (or lie in a cell)
+    reproduces that node's (cell's) full value bit for bit: both sums take the
+    same terms in the same ascending order."""
+    p, m = jbox
+    rp_, ci = m.pattern()
+    Kb = np.random.default_rng(19).standard_normal(m.nnz)
+    dE, dX = m.backward(Kb)
+    gp_ptr, gp_nbr = m.support()
+    owner = np.repeat(np.arange(p.n_gp), np.diff(gp_ptr))
+    for node in (0, 77, p.n_nodes - 1):
+        gps = np.unique(owner[gp_nbr == node])
+        _, dXs = m.backward(Kb, gps=gps)
+        assert np.array_equal(dXs[node], dX[node])
+    for cell in (0, 64, p.n_cells - 1):
+        gps = np.where(p.gp_cell == cell)[0]
+        dEs, _ = m.backward(Kb, gps=gps)
+        assert dEs[cell] == dE[cell]
+        assert np.count_nonzero(dEs) == 1
+    # splitting the points into two halves adds up to the whole
+    half = p.n_gp // 2
+    a = m.backward(Kb, gps=np.arange(half))
+    b = m.backward(Kb, gps=np.arange(half, p.n_gp))
+    assert np.allclose(a[1] + b[1], dX, rtol=1e-12, atol=1e-12 * np.abs(dX).max())
