@@ -11,7 +11,9 @@
 //         sides eliminated as extra columns; back substitution k descending.
 //   k_IJ: e = fma(lc, m1, mc*m2), m1 = pI_al pJ_be, m2 = pI_be pJ_al (+ dot),
 //         dot = fma(pI2,pJ2, fma(pI1,pJ1, pI0 pJ0)).
-//   K   : +0 + e_g1 + e_g2 + ... over contributing points in ascending g.
+//   K   : +0 + e_g1 + e_g2 + ... over contributing points in ascending g;
+//         mixed: float terms, one compensated (Kahan) float sum per entry,
+//         also in ascending g.
 #include <cfloat>
 #include <climits>
 #include <cstdlib>
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* acc = smem;                 // [L][9] double sums (both precisions)
+  double* acc = smem;                 // [L][9] double sums, or (sum, compensation) float pairs (mixed)
   uint2* bm = (uint2*)(acc + 9 * L);  // row I's rank bitmap
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   const int nw = (int)(rbm_off[I + 1] - wb);
   constexpr int kThreadsG = 64 * GW;
   for (int i = tid; i < nw; i += kThreadsG) bm[i] = rbm[wb + i];
-  for (int i = tid; i < 9 * L; i += kThreadsG) acc[i] = 0.0;
+  for (int i = tid; i < 9 * L; i += kThreadsG) acc[i] = 0.0;  // +0 sums and compensations
   // this wave's columns: node ids in [thr_lo, thr_hi)
   const int32_t thr_lo = w == 0 ? INT_MIN : blk_col[rb + (int64_t)w * L / GW];
   const int32_t thr_hi = w + 1 == GW ? INT_MAX : blk_col[rb + (int64_t)(w + 1) * L / GW];
@@ -338,7 +340,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
       for (int al = 0; al < 3; ++al)
 #pragma unroll
         for (int be = 0; be < 3; ++be) m[al][be] = pI[al] * pJ[be];
-      double* a = acc + 9 * pos;
+      float2* a = reinterpret_cast<float2*>(acc) + 9 * pos;
 #pragma unroll
       for (int al = 0; al < 3; ++al)
 #pragma unroll
@@ -346,8 +348,17 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
           float m2 = m[be][al];
           if (al == be) m2 = m2 + dot;
           const float ev = __builtin_fmaf(flc, m[al][be], fmc * m2);
-          // the float term joins the slot's double sum (ds_add_f64, in ascending g)
-          __hip_atomic_fetch_add(a + 3 * al + be, (double)ev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          // compensated float sum (Kahan): the slot holds (sum, compensation);
+          // the compensation keeps the low-order part that the rounded sum
+          // dropped and feeds it back with the next term.  The lane owns the
+          // slot for this point and the wave's LDS operations run in program
+          // order, so the next point's read sees this write (ascending g).
+          float2 sc = a[3 * al + be];
+          const float y = ev - sc.y;
+          const float t = sc.x + y;
+          sc.y = (t - sc.x) - y;
+          sc.x = t;
+          a[3 * al + be] = sc;
         }
     }
   };
@@ -387,7 +398,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
     const int pos = idx / 9, r = idx - 9 * pos, a = r / 3, be = r - 3 * a;
     const int64_t o = base + 3 * (int64_t)a * L + 3 * pos + be;
     if (!kMixed) ((double*)Kout)[o] = acc[idx];
-    else ((float*)Kout)[o] = (float)acc[idx];  // one rounding of the double sum
+    else ((float*)Kout)[o] = reinterpret_cast<const float2*>(acc)[idx].x;  // the compensated sum
   }
 }
 
