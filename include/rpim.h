@@ -58,7 +58,7 @@ typedef enum {
 typedef enum {
   RPIM_FP64 = 0,  /* K is double[nnz]; everything FP64                         */
   RPIM_MIXED = 1  /* K is float[nnz]: FP64 moment matrix + LU, FP32 B^T D B,
-                     each entry summed in FP64, rounded once to FP32           */
+                     each entry a compensated (Kahan) FP32 sum in ascending g  */
 } rpim_precision;
 
 /* One model, or a block-diagonal batch of independent models.
@@ -152,20 +152,34 @@ rpim_status rpim_assemble_backward(rpim_plan* plan, const double* node_xyz, cons
                                    double nu, const double* dK_vals, double* dE_cell, double* dX_node,
                                    void* stream);
 
-/* Stage 2: penalty boundary conditions (GeoMFree3D Sec. 2; one GPU thread per
- * fixed dof).  alpha = factor * max_i K_ii over all n_dof diagonals (before the
- * update); K_dd += alpha and, if rhs != NULL, rhs_d += alpha * u_bar_d
- * (u_bar may be NULL = zero).  fixed_dof int32[n_fixed] must be strictly
- * ascending and in [0, n_dof) (checked, RPIM_E_ARG; the check synchronises).
+/* Stage 2: penalty boundary conditions (GeoMFree3D Sec. 2, stage 2: the
+ * constraints are imposed by a penalty on the assembled system, one GPU
+ * thread per fixed dof).  alpha = factor * max_i K_ii over all n_dof
+ * diagonals (before the update); K_dd += alpha and, if rhs != NULL,
+ * rhs_d += alpha * u_bar_d (u_bar may be NULL = zero) for each fixed dof d.
  * K_vals is double or float per `precision`; for float, K_dd += (float)alpha.
- * If alpha_out != NULL the value of alpha is written there (host). */
+ *   fixed_dof int32[n_fixed]: strictly ascending, in [0, n_dof), each with a
+ *             diagonal entry in the pattern.  Checked on the device: if the
+ *             check fails, K and rhs are left unchanged and *status gets
+ *             RPIM_E_ARG (RPIM_OK otherwise).
+ *   alpha     device double receiving alpha, or NULL.
+ *   status    device int32 receiving the check's result, or NULL.
+ *   workspace caller-owned device memory of at least
+ *             rpim_penalty_workspace_bytes(n_dof, n_fixed) bytes (8-byte
+ *             aligned); it may be reused once the call's kernels are done.
+ * Asynchronous: kernels only (no host synchronisation, allocation or memset),
+ * so the call can be recorded into a graph.  Argument errors found on the host
+ * (NULL pointers, n_dof <= 0, a non-positive factor, a short workspace) return
+ * RPIM_E_ARG before anything runs; n_dof > 2^31 - 1 returns RPIM_E_RANGE. */
+size_t rpim_penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed);
 rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals,
                                   int precision, int64_t n_dof, const int32_t* fixed_dof,
                                   const double* u_bar, int64_t n_fixed, double factor, double* rhs,
-                                  double* alpha_out, void* stream);
+                                  double* alpha, int32_t* status, void* workspace, size_t workspace_bytes,
+                                  void* stream);
 
-/* Launch-configuration tuning (synchronous).  Evaluates the pair table and the
- * moment-matrix solves once, then times the row gather of `precision` with 2,
+/* Launch-configuration tuning (synchronous).  Kept LU factors are invalidated.
+ * Evaluates the pair table and the moment-matrix solves once, then times the row gather of `precision` with 2,
  * 3 and 4 waves per node row on this plan's own data and keeps the fastest for
  * later rpim_assemble calls with that precision (each configuration computes
  * the same bits; only speed differs).  K_vals (nnz values of the precision's
@@ -186,6 +200,25 @@ rpim_status rpim_autotune(rpim_plan* plan, const double* node_xyz, const double*
 /* Set the row-gather configuration (2, 3 or 4 waves per node row) for
  * `precision` by hand, as rpim_autotune would; RPIM_E_ARG otherwise. */
 rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
+
+/* Moment-matrix solver kernel of the support-size bucket holding padded size
+ * nmax = n + 4 (nmax = 0: every bucket).  Every kernel computes the same bits
+ * (the elimination order of the arithmetic contract); only speed differs.
+ *   RPIM_SOLVER_AUTO   the library's choice (default)
+ *   RPIM_SOLVER_LDS    the whole augmented matrix in LDS (any size up to 136)
+ *   RPIM_SOLVER_WINDOW one matrix row per thread in registers (N <= 104)
+ * Buckets a kernel cannot hold fall back to the LDS kernel.  RPIM_E_ARG for
+ * an unknown kind or nmax outside [0, 136]. */
+enum { RPIM_SOLVER_AUTO = 0, RPIM_SOLVER_LDS = 1, RPIM_SOLVER_WINDOW = 2 };
+rpim_status rpim_set_solver(rpim_plan* plan, int nmax, int kind);
+
+/* Identifier of the LU factors the plan currently keeps for the backward: a
+ * new positive value after each rpim_assemble with keep_factors = 1, 0 once
+ * they are gone (an assembly without keep_factors, rpim_autotune or
+ * rpim_rebuild_pattern overwrite the state they belong to).  A caller that
+ * saves it at the forward can check, before rpim_assemble_backward, that the
+ * factors still belong to that forward. */
+rpim_status rpim_factor_generation(const rpim_plan* plan, int64_t* gen);
 
 /* Synchronise `stream` and report device-side errors of the plan's last calls:
  * the most severe status and the smallest failing Gauss-point id (-1 if none).

@@ -70,7 +70,9 @@ def lib():
         L.rpim_build_pattern.argtypes = [vp, vp, vp, C.POINTER(i64), vp]
         L.rpim_assemble.argtypes = [vp, vp, vp, d, i32, i32, vp, vp]
         L.rpim_assemble_backward.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
-        L.rpim_apply_penalty_bc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, C.POINTER(d), vp]
+        L.rpim_apply_penalty_bc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, vp, vp, vp, C.c_size_t, vp]
+        L.rpim_penalty_workspace_bytes.argtypes = [i64, i64]
+        L.rpim_penalty_workspace_bytes.restype = C.c_size_t
         L.rpim_get_status.argtypes = [vp, vp, C.POINTER(i64)]
         L.rpim_plan_info.argtypes = [vp, C.POINTER(_Info)]
         L.rpim_get_support.argtypes = [vp, vp, vp, vp]
@@ -81,13 +83,16 @@ def lib():
         L.rpim_profile_read.argtypes = [vp, C.POINTER(d)]
         L.rpim_autotune.argtypes = [vp, vp, vp, d, i32, vp, vp, C.POINTER(_Tuning)]
         L.rpim_set_gather_waves.argtypes = [vp, i32, i32]
+        L.rpim_set_solver.argtypes = [vp, i32, i32]
+        L.rpim_factor_generation.argtypes = [vp, C.POINTER(i64)]
         L.rpim_plan_destroy.argtypes = [vp]
         L.rpim_plan_destroy.restype = None
         L.rpim_status_string.restype = C.c_char_p
         for f in ("rpim_plan_create", "rpim_build_pattern", "rpim_assemble", "rpim_assemble_backward",
                   "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
                   "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
-                  "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves"):
+                  "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves", "rpim_set_solver",
+                  "rpim_factor_generation"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -239,6 +244,19 @@ class Plan:
     def set_gather_waves(self, precision, waves: int):
         _check(lib().rpim_set_gather_waves(self._h, _precision(precision), int(waves)), "rpim_set_gather_waves")
 
+    SOLVERS = {"auto": 0, "lds": 1, "window": 2}
+
+    def set_solver(self, kind, nmax: int = 0):
+        """Moment-matrix solver kernel for the bucket of padded size nmax (0: all buckets)."""
+        k = self.SOLVERS[kind] if isinstance(kind, str) else int(kind)
+        _check(lib().rpim_set_solver(self._h, int(nmax), k), "rpim_set_solver")
+
+    def factor_generation(self) -> int:
+        """Identifier of the kept LU factors (0: none)."""
+        g = C.c_int64()
+        _check(lib().rpim_factor_generation(self._h, C.byref(g)), "rpim_factor_generation")
+        return g.value
+
     # -- forward / backward ----------------------------------------------------
     def assemble(self, node_xyz=None, cell_E=None, nu=0.3, precision=FP64, keep_factors=False, out=None):
         torch = _torch()
@@ -297,17 +315,31 @@ def _precision(p):
     raise ValueError(f"unknown precision {p!r}")
 
 
-def apply_penalty_bc(row_ptr, col_idx, K, fixed_dof, u_bar=None, factor=1e8, rhs=None):
-    """Penalty BCs in place on K (float64 or float32) and rhs; returns alpha (synchronises)."""
+def apply_penalty_bc(row_ptr, col_idx, K, fixed_dof, u_bar=None, factor=1e8, rhs=None, check=True):
+    """Penalty BCs in place on K (float64 or float32) and rhs, on the current stream.
+
+    With check=True (default) the call synchronises, raises RpimError(RPIM_E_ARG) if the device check of
+    the fixed dofs failed (K and rhs are then unchanged) and returns alpha as a float.  With check=False
+    nothing synchronises and (alpha, status) come back as one-element device tensors."""
     torch = _torch()
     prec = FP64 if K.dtype == torch.float64 else MIXED
     fx = _dev(fixed_dof, torch.int32, K.device)
     ub = None if u_bar is None else _dev(u_bar, torch.float64, K.device)
-    alpha = C.c_double()
-    _check(lib().rpim_apply_penalty_bc(_ptr(row_ptr), _ptr(col_idx), _ptr(K), prec, int(row_ptr.numel() - 1),
-                                       _ptr(fx), _ptr(ub), int(fx.numel()), float(factor), _ptr(rhs),
-                                       C.byref(alpha), _stream()), "rpim_apply_penalty_bc")
-    return alpha.value
+    n_dof = int(row_ptr.numel() - 1)
+    nbytes = lib().rpim_penalty_workspace_bytes(n_dof, int(fx.numel()))
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=K.device)
+    alpha = torch.empty(1, dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    _check(lib().rpim_apply_penalty_bc(_ptr(row_ptr), _ptr(col_idx), _ptr(K), prec, n_dof, _ptr(fx), _ptr(ub),
+                                       int(fx.numel()), float(factor), _ptr(rhs), _ptr(alpha), _ptr(status),
+                                       _ptr(ws), nbytes, _stream()), "rpim_apply_penalty_bc")
+    if not check:
+        return alpha, status
+    code = int(status.item())
+    if code != 0:
+        raise RpimError(code, "rpim_apply_penalty_bc", "(fixed dofs not strictly ascending in range, or a "
+                                                       "diagonal missing; K left unchanged)")
+    return float(alpha.item())
 
 
 def pow_cr(x, q):
@@ -330,12 +362,14 @@ def _make_fn():
             keep = bool(ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
             K = plan.assemble(node_xyz.detach(), cell_E.detach(), nu, precision, keep_factors=keep)
             ctx.plan, ctx.nu = plan, nu
+            ctx.factor_gen = plan.factor_generation() if keep else 0
             ctx.save_for_backward(node_xyz, cell_E)
             return K
 
         @staticmethod
         def backward(ctx, dK):
             X, E = ctx.saved_tensors
+            _check_factors(ctx.plan, ctx.factor_gen)
             dE, dX = ctx.plan.assemble_backward(X.detach(), E.detach(), ctx.nu, dK.detach().double().contiguous())
             return (dX if ctx.needs_input_grad[0] else None, dE if ctx.needs_input_grad[1] else None,
                     None, None, None)
@@ -344,6 +378,13 @@ def _make_fn():
 
 
 _AssembleFn = None
+
+
+def _check_factors(plan, gen):
+    """The backward reuses the LU factors its forward kept; raise if the plan has replaced them since."""
+    if gen == 0 or plan.factor_generation() != gen:
+        raise RpimError(-8, "assemble backward",
+                        "(the plan's kept factors belong to another forward: run the forward again)")
 
 
 def assemble(plan: Plan, node_xyz, cell_E, nu=0.3, precision=FP64):

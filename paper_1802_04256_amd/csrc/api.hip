@@ -4,7 +4,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "rpim_internal.h"
 
@@ -31,6 +33,25 @@ rpim_status ensure_alloc(void** p, int64_t* cap, int64_t count, size_t elem) {
     return hip_ok(e);
   }
   *cap = count;
+  return RPIM_OK;
+}
+
+rpim_status raise_lds_limit(const void* fn, size_t lds, int device) {
+  struct Entry {
+    const void* fn;
+    int device;
+    size_t lds;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> set;
+  std::lock_guard<std::mutex> lock(mu);
+  Entry* e = nullptr;
+  for (Entry& x : set)
+    if (x.fn == fn && x.device == device) e = &x;
+  if (e && lds <= e->lds) return RPIM_OK;
+  RPIM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (e) e->lds = lds;
+  else set.push_back(Entry{fn, device, lds});
   return RPIM_OK;
 }
 
@@ -196,12 +217,9 @@ rpim_status rpim_rebuild_pattern(rpim_plan* p, const double* node_xyz, int64_t* 
   if ((row_ptr == nullptr) != (col_idx == nullptr)) return RPIM_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   RPIM_HIP(hipStreamSynchronize(s));
-  dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
-  dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->lu_off);
-  dfree(p->cell_ptr); dfree(p->cell_gp); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
-  p->built = false;
+  free_pattern(p);
   p->have_factors = false;
-  p->buckets.clear();
+  ++p->factor_gen;
   RPIM_HIP(hipMemcpyAsync(p->node_xyz0, node_xyz, sizeof(double) * 3 * p->N, hipMemcpyDeviceToDevice, s));
   return rpim_build_pattern(p, row_ptr, col_idx, nnz, stream);
 }
@@ -241,6 +259,7 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
         (st = ensure(&p->gam, &p->cap_gam, 3 * (p->sum_n + 4 * p->G))))
       return st;
   }
+  if (p->have_factors) ++p->factor_gen;
   p->have_factors = false;
   phase_begin(p, RPIM_PHASE_PAIRS, s);
   if ((st = launch_pair_table(p, node_xyz, s)) != RPIM_OK) return st;
@@ -254,6 +273,7 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
   if ((st = launch_rowgather(p, cell_E, nu, precision, K_vals, s)) != RPIM_OK) return st;
   phase_end(p, RPIM_PHASE_GATHER, s);
   p->have_factors = keep_factors != 0;
+  if (p->have_factors) ++p->factor_gen;
   return RPIM_OK;
 }
 
@@ -276,6 +296,9 @@ rpim_status rpim_autotune(rpim_plan* p, const double* node_xyz, const double* ce
   if ((st = ensure(&p->R, &p->cap_R, p->nblk)) || (st = ensure(&p->dphi, &p->cap_dphi, 3 * p->sum_n))) return st;
   if (precision == RPIM_MIXED && (st = ensure(&p->dphi32, &p->cap_dphi32, 3 * p->sum_n))) return st;
   float* d32 = precision == RPIM_MIXED ? p->dphi32 : nullptr;
+  // the runs below rewrite the pair table and the gradients that kept factors belong to
+  if (p->have_factors) ++p->factor_gen;
+  p->have_factors = false;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   RPIM_HIP(hipEventCreate(&e0));
   if (hip_ok(hipEventCreate(&e1)) != RPIM_OK) {
@@ -331,14 +354,35 @@ rpim_status rpim_set_gather_waves(rpim_plan* p, int precision, int waves) {
   return RPIM_OK;
 }
 
+size_t rpim_penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed) {
+  if (n_dof <= 0 || n_fixed < 0) return 0;
+  return penalty_workspace_bytes(n_dof, n_fixed);
+}
+
 rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, int precision,
                                   int64_t n_dof, const int32_t* fixed_dof, const double* u_bar, int64_t n_fixed,
-                                  double factor, double* rhs, double* alpha_out, void* stream) {
+                                  double factor, double* rhs, double* alpha, int32_t* status, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
   if (!row_ptr || !col_idx || !K_vals || n_dof <= 0 || n_fixed < 0 || (n_fixed > 0 && !fixed_dof)) return RPIM_E_ARG;
+  if (n_dof > INT32_MAX) return RPIM_E_RANGE;
   if (precision != RPIM_FP64 && precision != RPIM_MIXED) return RPIM_E_ARG;
   if (!(factor > 0) || !std::isfinite(factor)) return RPIM_E_ARG;
-  return launch_penalty(row_ptr, col_idx, K_vals, precision, n_dof, fixed_dof, u_bar, n_fixed, factor, rhs,
-                        alpha_out, (hipStream_t)stream);
+  return launch_penalty(row_ptr, col_idx, K_vals, precision, n_dof, fixed_dof, u_bar, n_fixed, factor, rhs, alpha,
+                        status, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+rpim_status rpim_set_solver(rpim_plan* p, int nmax, int kind) {
+  if (!p || nmax < 0 || nmax > kMaxSupport + 4) return RPIM_E_ARG;
+  if (kind != RPIM_SOLVER_AUTO && kind != RPIM_SOLVER_LDS && kind != RPIM_SOLVER_WINDOW) return RPIM_E_ARG;
+  for (int b = 0; b < kMaxBuckets; ++b)
+    if (nmax == 0 || b == (nmax + kBucketStep - 1) / kBucketStep) p->solver_kind[b] = (int8_t)kind;
+  return RPIM_OK;
+}
+
+rpim_status rpim_factor_generation(const rpim_plan* p, int64_t* gen) {
+  if (!p || !gen) return RPIM_E_ARG;
+  *gen = p->have_factors ? p->factor_gen : 0;
+  return RPIM_OK;
 }
 
 rpim_status rpim_get_status(rpim_plan* p, void* stream, int64_t* first_bad_gp) {

@@ -16,8 +16,6 @@
 //         also in ascending g.
 #include <cfloat>
 #include <climits>
-#include <cstdlib>
-
 #include <type_traits>
 
 #include "dd_pow.h"
@@ -232,12 +230,13 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
                                                               const int64_t* gp_ptr, const int32_t* gp_nbr,
                                                               const void* dphi_any, const double* wdet,
                                                               const int32_t* gp_cell, const double* E, double lam,
-                                                              double mu, void* Kout) {
+                                                              double mu, void* Kout, int64_t n_rows) {
   extern __shared__ double smem[];
   // gradients: FP64, or rounded to float by the solver for the mixed path
   using T = typename std::conditional<kMixed, float, double>::type;
   const T* dphi = static_cast<const T*>(dphi_any);
-  const int64_t I = blockIdx.x;
+  const int64_t I = xcd_row(blockIdx.x, n_rows);
+  if (I >= n_rows) return;  // padding workgroup (uniform)
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
   double* acc = smem;                 // [L][9] double sums, or (sum, compensation) float pairs (mixed)
@@ -404,16 +403,6 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Raise a kernel's dynamic-LDS limit only when a launch needs more than was
-// set before, so launches recorded into a graph make no attribute calls once
-// the plan has run eagerly.
-rpim_status lds_limit(const void* fn, size_t lds, size_t* cur) {
-  if (lds <= *cur) return RPIM_OK;
-  RPIM_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  *cur = lds;
-  return RPIM_OK;
-}
-size_t g_lds_shape = 0;
 
 }  // namespace
 
@@ -431,14 +420,13 @@ rpim_status launch_shape_bucket(rpim_plan* p, const Bucket& b, const double* X, 
                                 hipStream_t s) {
   const double ac = p->alpha_c * p->d_c;
   const double C2 = ac * ac;
-  const char* sel = getenv("RPIM_SHAPE_KERNEL");
-  const bool use_reg = !(sel && sel[0] == 'l');  // "lds" selects the shared-memory kernel for every bucket
-  if (use_reg && b.nmax <= shape_reg_max()) return launch_shape_reg(p, b, X, C2, keep, dphi32, s);
+  const int kind = p->solver_kind[b.nmax / kBucketStep];
+  if (kind != RPIM_SOLVER_LDS && b.nmax <= shape_reg_max()) return launch_shape_reg(p, b, X, C2, keep, dphi32, s);
   const int N = b.nmax;
   const int ld = ((N + 3) | 1);  // odd row stride in doubles
   const size_t lds = sizeof(double) * (size_t)N * ld + sizeof(int) * (size_t)(2 * N);
   if (lds > 160 * 1024) return RPIM_E_RANGE;
-  if (rpim_status st = lds_limit((const void*)k_shape, lds, &g_lds_shape)) return st;
+  if (rpim_status st = raise_lds_limit((const void*)k_shape, lds, p->device)) return st;
   hipLaunchKernelGGL(k_shape, dim3((unsigned)b.count), dim3(kThreads), lds, s, (const int32_t*)p->gp_order,
                      b.begin, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const int64_t*)p->blk_ptr,
                      (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
@@ -456,14 +444,13 @@ rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32,
 
 template <bool kMixed, int GW>
 rpim_status launch_gather_t(rpim_plan* p, const double* E, double lam, double mu, void* K, size_t lds, hipStream_t s) {
-  static size_t lds_set = 0;
-  if (rpim_status st = lds_limit((const void*)k_rowgather<kMixed, GW>, lds, &lds_set)) return st;
-  hipLaunchKernelGGL((k_rowgather<kMixed, GW>), dim3((unsigned)p->N), dim3(64 * GW), lds, s,
+  if (rpim_status st = raise_lds_limit((const void*)k_rowgather<kMixed, GW>, lds, p->device)) return st;
+  hipLaunchKernelGGL((k_rowgather<kMixed, GW>), dim3((unsigned)xcd_rows_grid(p->N)), dim3(64 * GW), lds, s,
                      (const int64_t*)p->blk_ptr, (const int32_t*)p->blk_col, (const int32_t*)p->row_lo,
                      (const int64_t*)p->rbm_off, (const uint2*)p->rbm, (const int64_t*)p->inv_ptr,
                      (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
                      kMixed ? (const void*)p->dphi32 : (const void*)p->dphi, (const double*)p->gp_wdet,
-                     (const int32_t*)p->gp_cell, E, lam, mu, K);
+                     (const int32_t*)p->gp_cell, E, lam, mu, K, p->N);
   RPIM_HIP(hipGetLastError());
   return RPIM_OK;
 }

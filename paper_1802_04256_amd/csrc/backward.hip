@@ -69,9 +69,11 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
                                                  const int64_t* inv_ptr, const uint64_t* inv_key,
                                                  const int64_t* gp_ptr, const int32_t* gp_nbr, const double* dphi,
                                                  const double* wdet, const int32_t* gp_cell, const double* E,
-                                                 double lam, double mu, const double* M, double* pbar, double* dEs) {
+                                                 double lam, double mu, const double* M, double* pbar, double* dEs,
+                                                 int64_t n_rows) {
   extern __shared__ double smem[];
-  const int64_t I = blockIdx.x;
+  const int64_t I = xcd_row(blockIdx.x, n_rows);
+  if (I >= n_rows) return;  // padding workgroup (uniform)
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
   double* Mrow = smem;                  // [L][9]  M_IJ blocks of row I
@@ -408,13 +410,13 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   const int L = (int)p->max_row_blocks;
   const size_t lds_rows = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds_rows > 160 * 1024) return RPIM_E_RANGE;
-  RPIM_HIP(hipFuncSetAttribute((const void*)k_bwd_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_rows));
-  hipLaunchKernelGGL(k_bwd_rows, dim3((unsigned)p->N), dim3(kT), lds_rows, s, (const int64_t*)p->blk_ptr,
+  if ((st = raise_lds_limit((const void*)k_bwd_rows, lds_rows, p->device)) != RPIM_OK) return st;
+  hipLaunchKernelGGL(k_bwd_rows, dim3((unsigned)xcd_rows_grid(p->N)), dim3(kT), lds_rows, s, (const int64_t*)p->blk_ptr,
                      (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                      (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                      (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, (const double*)p->msym,
-                     p->pbar, p->dEs);
+                     p->pbar, p->dEs, p->N);
   RPIM_HIP(hipGetLastError());
   phase_end(p, RPIM_PHASE_BWD_ROWS, s);
   phase_begin(p, RPIM_PHASE_BWD_GP, s);

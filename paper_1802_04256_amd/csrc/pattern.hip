@@ -330,20 +330,76 @@ __global__ void k_expand_cols(int64_t nblk, const int64_t* blk_ptr, const int32_
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Device temporaries of one pattern build, freed on every exit path (the
+// stream is synchronised first, so no kernel still uses them).
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t s) : s_(s) {}
+  ~Scratch() {
+    if (ptrs_.empty()) return;
+    (void)hipStreamSynchronize(s_);
+    for (void* q : ptrs_) (void)hipFree(q);
+  }
+  template <class T>
+  rpim_status alloc(T** out, int64_t count) {
+    *out = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+    if (e != hipSuccess) return hip_ok(e);
+    ptrs_.push_back(q);
+    *out = static_cast<T*>(q);
+    return RPIM_OK;
+  }
+  // hand a temporary over to the plan (not freed here)
+  template <class T>
+  void release(T* q) {
+    for (size_t i = 0; i < ptrs_.size(); ++i)
+      if (ptrs_[i] == (void*)q) {
+        ptrs_.erase(ptrs_.begin() + (long)i);
+        return;
+      }
+  }
+
+ private:
+  hipStream_t s_;
+  std::vector<void*> ptrs_;
+};
+
+template <class T>
+void dfree(T*& q) {
+  if (q) (void)hipFree(q);
+  q = nullptr;
+}
+
 }  // namespace
+
+void free_pattern(rpim_plan* p) {
+  dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
+  dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->lu_off);
+  dfree(p->cell_ptr); dfree(p->cell_gp); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
+  p->built = false;
+  p->buckets.clear();
+}
 
 rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   const int M = p->n_models;
   const int64_t N = p->N, G = p->G;
+  RPIM_HIP(hipStreamSynchronize(s));
+  free_pattern(p);  // arrays of an earlier (possibly failed) build
+  Scratch tmp(s);
+  rpim_status st = RPIM_OK;
+#define RPIM_TRY(x)                   \
+  do {                                \
+    if ((st = (x)) != RPIM_OK) return st; \
+  } while (0)
   // bounding boxes -> bin grids (host)
   double* d_bb = nullptr;
-  RPIM_HIP(hipMalloc((void**)&d_bb, sizeof(double) * 6 * M));
+  RPIM_TRY(tmp.alloc(&d_bb, 6 * M));
   hipLaunchKernelGGL(k_bbox, dim3(M), dim3(256), 0, s, X, (const int64_t*)p->d_node_off, d_bb);
   RPIM_HIP(hipGetLastError());
   std::vector<double> bb(6 * M);
   RPIM_HIP(hipMemcpyAsync(bb.data(), d_bb, sizeof(double) * 6 * M, hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipStreamSynchronize(s));
-  RPIM_HIP(hipFree(d_bb));
   std::vector<BinGrid> grids(M);
   int64_t nbins = 0;
   for (int m = 0; m < M; ++m) {
@@ -372,19 +428,18 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   int32_t *node_bin = nullptr, *bin_cnt = nullptr, *bin_nodes = nullptr, *counts = nullptr;
   int64_t* bin_start = nullptr;
   double* bxyz = nullptr;
-  RPIM_HIP(hipMalloc((void**)&d_grids, sizeof(BinGrid) * M));
+  RPIM_TRY(tmp.alloc(&d_grids, M));
   RPIM_HIP(hipMemcpyAsync(d_grids, grids.data(), sizeof(BinGrid) * M, hipMemcpyHostToDevice, s));
-  RPIM_HIP(hipMalloc((void**)&node_bin, sizeof(int32_t) * N));
-  RPIM_HIP(hipMalloc((void**)&bin_cnt, sizeof(int32_t) * nbins));
-  RPIM_HIP(hipMalloc((void**)&bin_start, sizeof(int64_t) * (nbins + 1)));
-  RPIM_HIP(hipMalloc((void**)&bin_nodes, sizeof(int32_t) * N));
-  RPIM_HIP(hipMalloc((void**)&bxyz, sizeof(double) * 3 * N));
+  RPIM_TRY(tmp.alloc(&node_bin, N));
+  RPIM_TRY(tmp.alloc(&bin_cnt, nbins));
+  RPIM_TRY(tmp.alloc(&bin_start, nbins + 1));
+  RPIM_TRY(tmp.alloc(&bin_nodes, N));
+  RPIM_TRY(tmp.alloc(&bxyz, 3 * N));
   RPIM_HIP(hipMemsetAsync(bin_cnt, 0, sizeof(int32_t) * nbins, s));
   hipLaunchKernelGGL(k_bin_count, dim3(nblocks(N, 256)), dim3(256), 0, s, X, N, (const int64_t*)p->d_node_off,
                      M, (const BinGrid*)d_grids, node_bin, bin_cnt);
   RPIM_HIP(hipGetLastError());
-  rpim_status st = exclusive_scan(bin_cnt, nbins, bin_start, s);
-  if (st != RPIM_OK) return st;
+  RPIM_TRY(exclusive_scan(bin_cnt, nbins, bin_start, s));
   RPIM_HIP(hipMemsetAsync(bin_cnt, 0, sizeof(int32_t) * nbins, s));
   hipLaunchKernelGGL(k_bin_fill, dim3(nblocks(N, 256)), dim3(256), 0, s, N, (const int32_t*)node_bin,
                      (const int64_t*)bin_start, bin_cnt, bin_nodes);
@@ -393,7 +448,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipGetLastError());
 
   // supports: count, scan, fill
-  RPIM_HIP(hipMalloc((void**)&counts, sizeof(int32_t) * std::max<int64_t>(G, N)));
+  RPIM_TRY(tmp.alloc(&counts, std::max<int64_t>(G, N)));
   RPIM_HIP(hipMalloc((void**)&p->gp_ptr, sizeof(int64_t) * (G + 1)));
   hipLaunchKernelGGL(k_support<false>, dim3(nblocks(G, 4)), dim3(256), 0, s, G, (const int64_t*)p->d_gp_off, M,
                      (const BinGrid*)d_grids, (const int64_t*)bin_start, (const int32_t*)bin_nodes,
@@ -405,8 +460,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipStreamSynchronize(s));
   if (hst.flags & kFlagRange) return RPIM_E_RANGE;
   if (hst.flags & kFlagSupport) return RPIM_E_SUPPORT;
-  st = exclusive_scan(counts, G, p->gp_ptr, s);
-  if (st != RPIM_OK) return st;
+  RPIM_TRY(exclusive_scan(counts, G, p->gp_ptr, s));
   std::vector<int64_t> gp_ptr_h(G + 1);
   RPIM_HIP(hipMemcpyAsync(gp_ptr_h.data(), p->gp_ptr, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipStreamSynchronize(s));
@@ -420,16 +474,14 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipGetLastError());
 
   // inverse lists
-  int32_t* cursor = bin_cnt;  // reuse when large enough
-  int32_t* inv_cnt = nullptr;
-  RPIM_HIP(hipMalloc((void**)&inv_cnt, sizeof(int32_t) * N));
-  RPIM_HIP(hipMalloc((void**)&cursor, sizeof(int32_t) * N));
+  int32_t *cursor = nullptr, *inv_cnt = nullptr;
+  RPIM_TRY(tmp.alloc(&inv_cnt, N));
+  RPIM_TRY(tmp.alloc(&cursor, N));
   RPIM_HIP(hipMemsetAsync(inv_cnt, 0, sizeof(int32_t) * N, s));
   hipLaunchKernelGGL(k_inv_count, dim3(nblocks(p->sum_n, 256)), dim3(256), 0, s, p->sum_n,
                      (const int32_t*)p->gp_nbr, inv_cnt);
   RPIM_HIP(hipMalloc((void**)&p->inv_ptr, sizeof(int64_t) * (N + 1)));
-  st = exclusive_scan(inv_cnt, N, p->inv_ptr, s);
-  if (st != RPIM_OK) return st;
+  RPIM_TRY(exclusive_scan(inv_cnt, N, p->inv_ptr, s));
   std::vector<int32_t> cnt_h(N);
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), inv_cnt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * N, s));
@@ -451,7 +503,8 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   // node-block rows
   int32_t *win_lo = nullptr, *win_len = nullptr, *blk_cnt = nullptr;
   RPIM_HIP(hipMalloc((void**)&win_lo, sizeof(int32_t) * N));
-  RPIM_HIP(hipMalloc((void**)&win_len, sizeof(int32_t) * N));
+  p->row_lo = win_lo;  // plan-owned from here (the window start of each row)
+  RPIM_TRY(tmp.alloc(&win_len, N));
   hipLaunchKernelGGL(k_window, dim3((unsigned)N), dim3(256), 0, s, N, (const int64_t*)p->inv_ptr,
                      (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, win_lo,
                      win_len);
@@ -484,8 +537,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
                      (const int64_t*)p->rbm_off, p->rbm);
   RPIM_HIP(hipGetLastError());
   RPIM_HIP(hipMalloc((void**)&p->blk_ptr, sizeof(int64_t) * (N + 1)));
-  st = exclusive_scan(blk_cnt, N, p->blk_ptr, s);
-  if (st != RPIM_OK) return st;
+  RPIM_TRY(exclusive_scan(blk_cnt, N, p->blk_ptr, s));
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), blk_cnt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
   int64_t nblk = 0;
   RPIM_HIP(hipMemcpyAsync(&nblk, p->blk_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -503,7 +555,6 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   // buckets by padded moment-matrix size, and LU offsets (host, from gp_ptr)
   p->min_n = INT32_MAX;
   p->max_n = 0;
-  constexpr int kBucketStep = 8;
   const int nb = (kMaxSupport + 4) / kBucketStep + 1;
   std::vector<int64_t> bcount(nb, 0);
   std::vector<int64_t> lu_off_h(G + 1, 0);
@@ -553,18 +604,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipMalloc((void**)&p->lu_off, sizeof(int64_t) * (G + 1)));
   RPIM_HIP(hipMemcpyAsync(p->lu_off, lu_off_h.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   RPIM_HIP(hipStreamSynchronize(s));
-
-  RPIM_HIP(hipFree(d_grids));
-  RPIM_HIP(hipFree(node_bin));
-  RPIM_HIP(hipFree(bin_cnt));
-  RPIM_HIP(hipFree(bin_start));
-  RPIM_HIP(hipFree(bin_nodes));
-  RPIM_HIP(hipFree(bxyz));
-  RPIM_HIP(hipFree(counts));
-  RPIM_HIP(hipFree(inv_cnt));
-  RPIM_HIP(hipFree(cursor));
-  p->row_lo = win_lo;
-  RPIM_HIP(hipFree(win_len));
+#undef RPIM_TRY
   p->built = true;
   return RPIM_OK;
 }

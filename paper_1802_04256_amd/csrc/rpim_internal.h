@@ -14,6 +14,8 @@ namespace rpim {
 constexpr int kMaxSupport = 132;        // nodes per support (N = n + 4 <= 136 fits the LDS solver)
 constexpr int kMaxInverse = 8192;       // supports containing one node
 constexpr int64_t kMaxWindow = 1 << 18; // node-id span of a node's neighbourhood
+constexpr int kBucketStep = 8;          // support-size buckets: padded N in steps of 8
+constexpr int kMaxBuckets = (kMaxSupport + 4) / kBucketStep + 1;
 
 // Device-side error record: smallest failing Gauss point and kinds seen.
 struct DevStatus {
@@ -40,6 +42,19 @@ __device__ __forceinline__ int64_t block_pos(const int64_t* blk_ptr, const int32
   const int r = J - row_lo[I];
   const uint2 w = rbm[rbm_off[I] + (r >> 5)];
   return blk_ptr[I] + (int64_t)w.y + __popc(w.x & ((1u << (r & 31)) - 1u));
+}
+
+// Row-major work over node rows, launched as 8 * ceil(n / 8) workgroups:
+// workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8),
+// so XCD x is given the contiguous rows [x * chunk, (x + 1) * chunk) in
+// ascending order.  Neighbouring rows share most of their Gauss points, so
+// this keeps those points' data in the L2 of the XCD that re-reads it.
+// Returns a row >= n for the padding workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int64_t xcd_rows_grid(int64_t n) { return kXcds * ((n + kXcds - 1) / kXcds); }
+__device__ __forceinline__ int64_t xcd_row(int64_t b, int64_t n) {
+  const int64_t chunk = (n + kXcds - 1) / kXcds;
+  return (b % kXcds) * chunk + b / kXcds;
 }
 
 struct Bucket {
@@ -88,6 +103,8 @@ struct rpim_plan {
   int64_t max_row_blocks = 0;    // longest node-block row
   int64_t max_inverse = 0;       // longest inverse list
   std::vector<rpim::Bucket> buckets;
+  // solver kernel per bucket (index nmax / kBucketStep): RPIM_SOLVER_* from rpim.h
+  int8_t solver_kind[rpim::kMaxBuckets] = {};
   int32_t* gp_order = nullptr;   // [G] Gauss points grouped by bucket
 
   // assembly workspace
@@ -105,6 +122,7 @@ struct rpim_plan {
   int32_t* piv = nullptr;        // [sum_n + 4G] per point at 4g + gp_ptr[g]
   double* gam = nullptr;         // [3 * (sum_n + 4G)] full solutions gamma_k per point
   bool have_factors = false;
+  int64_t factor_gen = 0;        // bumped whenever kept factors are written or invalidated
 
   // backward scratch and cell -> Gauss point lists
   double* msym = nullptr;        // [nnz]        dK + dK^T on the pattern
@@ -139,6 +157,10 @@ void phase_end(rpim_plan* p, int phase, hipStream_t s);
 
 // --- helpers (api.hip) -----------------------------------------------------
 rpim_status hip_ok(hipError_t e);
+// Raise a kernel's dynamic-LDS limit on `device` when a launch needs more than
+// was set before; once a plan has run eagerly, launches recorded into a graph
+// make no attribute calls.  Thread-safe; limits are per kernel and device.
+rpim_status raise_lds_limit(const void* fn, size_t lds, int device);
 // (Re)allocate *p to hold at least `count` elements; *cap tracks its capacity.
 rpim_status ensure_alloc(void** p, int64_t* cap, int64_t count, size_t elem);
 template <class T>
@@ -156,7 +178,10 @@ inline rpim_status ensure(T** p, int64_t* cap, int64_t count) {
 rpim_status exclusive_scan(const int32_t* counts, int64_t n, int64_t* out, hipStream_t s);
 
 // --- pattern.hip -------------------------------------------------------------
+// Builds supports, pattern, buckets and lists into the plan; frees the plan's
+// pattern arrays first and every temporary on each exit path.
 rpim_status build_pattern_device(rpim_plan* p, const double* node_xyz, hipStream_t s);
+void free_pattern(rpim_plan* p);
 rpim_status expand_pattern(const rpim_plan* p, int64_t* row_ptr, int32_t* col_idx, hipStream_t s);
 
 // --- assemble.hip ------------------------------------------------------------
@@ -179,8 +204,9 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
                             const double* dK, double* dE, double* dX, hipStream_t s);
 
 // --- penalty.hip -------------------------------------------------------------
-rpim_status launch_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision,
-                           int64_t n_dof, const int32_t* fixed, const double* ubar, int64_t n_fixed,
-                           double factor, double* rhs, double* alpha_out, hipStream_t s);
+size_t penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed);
+rpim_status launch_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision, int64_t n_dof,
+                           const int32_t* fixed, const double* ubar, int64_t n_fixed, double factor, double* rhs,
+                           double* alpha_out, int32_t* status_out, void* ws, size_t ws_size, hipStream_t s);
 
 }  // namespace rpim

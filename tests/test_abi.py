@@ -47,7 +47,11 @@ def test_plan_create_rejects_bad_arguments():
     assert lib.rpim_get_status(None, None, None) == -1
     assert lib.rpim_assemble(None, None, None, ctypes.c_double(0.3), 0, 0, None, None) == -1
     assert lib.rpim_apply_penalty_bc(None, None, None, 0, 0, None, None, 0, ctypes.c_double(1.0), None, None,
-                                     None) == -1
+                                     None, None, 0, None) == -1
+    assert lib.rpim_penalty_workspace_bytes(0, 0) == 0
+    assert lib.rpim_penalty_workspace_bytes(100, 10) >= 16 + 8 + 80
+    assert lib.rpim_set_solver(None, 0, 0) == -1
+    assert lib.rpim_factor_generation(None, None) == -1
     assert lib.rpim_autotune(None, None, None, ctypes.c_double(0.3), 0, None, None, None) == -1
 
 

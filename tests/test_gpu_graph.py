@@ -45,3 +45,39 @@ def test_graph_replay_matches_eager(precision):
         plan.assemble(X, E * (2.0 + rep), prob.nu, precision, out=K_other)
         torch.cuda.synchronize()
     plan.status()
+
+
+def test_graph_penalty_matches_eager():
+    # the penalty call records kernels only (no memset, no synchronisation): capture it with a copy of the
+    # assembled K in front, replay with eager work in between, compare K, rhs and alpha with an eager call
+    import torch
+    import paper_1802_04256_amd as rp
+    prob = W.cantilever()
+    print(f"[gpu case] graph penalty: gps={prob.n_gp}", flush=True)
+    dev = torch.device("cuda:0")
+    plan = rp.Plan.from_problem(prob, device=dev)
+    row_ptr, col_idx = plan.build_pattern()
+    K0 = plan.assemble(cell_E=prob.cell_E, nu=prob.nu)
+    X = prob.node_xyz
+    fixed = np.sort((3 * np.where(X[:, 0] == 0.0)[0][:, None] + np.arange(3)).ravel()).astype(np.int32)
+    ub = np.linspace(-1.0, 1.0, len(fixed))
+    K_ref, rhs_ref = K0.clone(), torch.zeros(3 * prob.n_nodes, dtype=torch.float64, device=dev)
+    alpha_ref = rp.apply_penalty_bc(row_ptr, col_idx, K_ref, fixed, u_bar=ub, rhs=rhs_ref)
+    fx = torch.from_numpy(fixed).to(dev)
+    ubt = torch.from_numpy(ub).to(dev)
+    K, rhs = torch.empty_like(K0), torch.empty_like(rhs_ref)
+    rp.apply_penalty_bc(row_ptr, col_idx, K0.clone(), fx, u_bar=ubt, rhs=rhs.zero_(), check=False)  # warm
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        K.copy_(K0)
+        rhs.zero_()
+        alpha, status = rp.apply_penalty_bc(row_ptr, col_idx, K, fx, u_bar=ubt, rhs=rhs, check=False)
+    for rep in range(3):
+        K.fill_(-1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0 and float(alpha.item()) == alpha_ref, rep
+        assert torch.equal(K, K_ref) and torch.equal(rhs, rhs_ref), rep
+        rp.apply_penalty_bc(row_ptr, col_idx, K0.clone(), fixed, factor=3.0)  # eager work between replays
+        torch.cuda.synchronize()

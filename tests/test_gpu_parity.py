@@ -144,11 +144,20 @@ def test_penalty_rejects_bad_fixed(rp):
     row_ptr = torch.from_numpy(S.indptr.astype(np.int64)).cuda()
     col_idx = torch.from_numpy(S.indices.astype(np.int32)).cuda()
     K = torch.from_numpy(S.data.copy()).cuda()
+    rhs = torch.ones(3, dtype=torch.float64, device="cuda")
     with pytest.raises(rp.RpimError) as ei:
-        rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([2, 1], np.int32))
+        rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([2, 1], np.int32), u_bar=np.ones(2), rhs=rhs)
     assert ei.value.code == -1
     with pytest.raises(rp.RpimError):
-        rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([3], np.int32))
+        rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([3], np.int32), rhs=rhs)
+    # a rejected call leaves K and rhs untouched; without the check nothing synchronises and the
+    # status word carries the result
+    assert np.array_equal(K.cpu().numpy(), [4.0, 5.0, 6.0]) and np.array_equal(rhs.cpu().numpy(), [1.0, 1.0, 1.0])
+    alpha, status = rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([-1], np.int32), check=False)
+    assert int(status.item()) == -1 and np.array_equal(K.cpu().numpy(), [4.0, 5.0, 6.0])
+    alpha, status = rp.apply_penalty_bc(row_ptr, col_idx, K, np.array([0, 2], np.int32), factor=2.0, check=False)
+    assert int(status.item()) == 0 and float(alpha.item()) == 12.0
+    assert np.array_equal(K.cpu().numpy(), [16.0, 5.0, 18.0])
 
 
 def test_cantilever_tip_deflection_from_gpu_K(rp):
@@ -231,13 +240,13 @@ def test_large_supports_lds_kernel_bitwise(rp, oracle_mod):
     assert np.array_equal(K, m.assemble())
 
 
-def test_lds_kernel_equals_register_kernel(rp, monkeypatch):
+def test_lds_kernel_equals_register_kernel(rp):
     prob = W.slope(L=12.0, W=8.0, H=6.0, x_c=3.0, jitter_seed=71, E_seed=72)
     plan = rp.Plan.from_problem(prob)
     plan.build_pattern()
     K_reg = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
     d_reg = plan.dphi().cpu().numpy()
-    monkeypatch.setenv("RPIM_SHAPE_KERNEL", "lds")
+    plan.set_solver("lds")
     K_lds = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
     d_lds = plan.dphi().cpu().numpy()
     plan.status()
