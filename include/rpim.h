@@ -178,6 +178,21 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
                                   double* alpha, int32_t* status, void* workspace, size_t workspace_bytes,
                                   void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): rpim_apply_penalty_bc
+ * with the library's own device scratch in place of the workspace; the same
+ * kernels, arguments, outputs and device-side check.  The scratch is a static
+ * array of about 2 MB per GPU (held until the process ends), so n_fixed may be
+ * at most RPIM_PENALTY_NOALLOC_MAX_FIXED (RPIM_E_RANGE beyond, before anything
+ * runs).  Every call on one GPU uses that GPU's scratch: calls that overlap on
+ * one GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Nothing in the scratch needs clearing between calls. */
+#define RPIM_PENALTY_NOALLOC_MAX_FIXED (1 << 18)
+rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals,
+                                          int precision, int64_t n_dof, const int32_t* fixed_dof,
+                                          const double* u_bar, int64_t n_fixed, double factor, double* rhs,
+                                          double* alpha, int32_t* status, void* stream);
+
 /* Launch-configuration tuning (synchronous).  Kept LU factors are invalidated.
  * Evaluates the pair table and the moment-matrix solves once, then times the row gather of `precision` with 2,
  * 3 and 4 waves per node row on this plan's own data and keeps the fastest for

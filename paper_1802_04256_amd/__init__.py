@@ -15,6 +15,7 @@ import numpy as np
 __all__ = ["Plan", "assemble", "apply_penalty_bc", "pow_cr", "RpimError", "library_path", "FP64", "MIXED"]
 
 FP64, MIXED = 0, 1
+PENALTY_NOALLOC_MAX_FIXED = 1 << 18  # RPIM_PENALTY_NOALLOC_MAX_FIXED in rpim.h
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "librpim.so")
 
@@ -71,6 +72,7 @@ def lib():
         L.rpim_assemble.argtypes = [vp, vp, vp, d, i32, i32, vp, vp]
         L.rpim_assemble_backward.argtypes = [vp, vp, vp, d, vp, vp, vp, vp]
         L.rpim_apply_penalty_bc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, vp, vp, vp, C.c_size_t, vp]
+        L.rpim_apply_penalty_bc_noalloc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, vp, vp, vp]
         L.rpim_penalty_workspace_bytes.argtypes = [i64, i64]
         L.rpim_penalty_workspace_bytes.restype = C.c_size_t
         L.rpim_get_status.argtypes = [vp, vp, C.POINTER(i64)]
@@ -92,7 +94,7 @@ def lib():
                   "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
                   "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
                   "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves", "rpim_set_solver",
-                  "rpim_factor_generation"):
+                  "rpim_factor_generation", "rpim_apply_penalty_bc_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib

@@ -371,6 +371,18 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
                         status, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
+rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals,
+                                          int precision, int64_t n_dof, const int32_t* fixed_dof,
+                                          const double* u_bar, int64_t n_fixed, double factor, double* rhs,
+                                          double* alpha, int32_t* status, void* stream) {
+  if (!row_ptr || !col_idx || !K_vals || n_dof <= 0 || n_fixed < 0 || (n_fixed > 0 && !fixed_dof)) return RPIM_E_ARG;
+  if (n_dof > INT32_MAX) return RPIM_E_RANGE;
+  if (precision != RPIM_FP64 && precision != RPIM_MIXED) return RPIM_E_ARG;
+  if (!(factor > 0) || !std::isfinite(factor)) return RPIM_E_ARG;
+  return launch_penalty_noalloc(row_ptr, col_idx, K_vals, precision, n_dof, fixed_dof, u_bar, n_fixed, factor, rhs,
+                                alpha, status, (hipStream_t)stream);
+}
+
 rpim_status rpim_set_solver(rpim_plan* p, int nmax, int kind) {
   if (!p || nmax < 0 || nmax > kMaxSupport + 4) return RPIM_E_ARG;
   if (kind != RPIM_SOLVER_AUTO && kind != RPIM_SOLVER_LDS && kind != RPIM_SOLVER_WINDOW) return RPIM_E_ARG;

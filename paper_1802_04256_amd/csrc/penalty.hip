@@ -17,6 +17,7 @@
 #include <cfloat>
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "rpim_internal.h"
 
@@ -143,7 +144,7 @@ __global__ void k_apply(T* K, const int32_t* fixed, const int64_t* pos, const do
   }
 }
 
-// The launch sequence of one call; ws holds ws_bytes(n_dof, n_fixed) bytes.
+// The launch sequence shared by both entry points; ws holds ws_bytes(n_dof, n_fixed) bytes.
 rpim_status penalty_launch(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision, int64_t n_dof,
                            const int32_t* fixed, const double* ubar, int64_t n_fixed, double factor, double* rhs,
                            double* alpha_out, int32_t* status_out, void* ws, hipStream_t s) {
@@ -171,6 +172,33 @@ rpim_status penalty_launch(const int64_t* row_ptr, const int32_t* col_idx, void*
   return RPIM_OK;
 }
 
+// ---- library-owned scratch for callers that cannot allocate -----------------
+// One copy per GPU, held until the process ends.  Host code never uses the
+// array's name as an address: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t kNoallocMaxFixed = RPIM_PENALTY_NOALLOC_MAX_FIXED;
+constexpr size_t kNoallocBytes = 16 + sizeof(double) * kMaxParts + sizeof(int64_t) * kNoallocMaxFixed;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+rpim_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  RPIM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return RPIM_E_RANGE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    RPIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return RPIM_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RPIM_OK;
+}
+
 }  // namespace
 
 size_t penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed) { return ws_bytes(n_dof, n_fixed); }
@@ -179,6 +207,17 @@ rpim_status launch_penalty(const int64_t* row_ptr, const int32_t* col_idx, void*
                            const int32_t* fixed, const double* ubar, int64_t n_fixed, double factor, double* rhs,
                            double* alpha_out, int32_t* status_out, void* ws, size_t ws_size, hipStream_t s) {
   if (!ws || ws_size < ws_bytes(n_dof, n_fixed) || (reinterpret_cast<uintptr_t>(ws) & 7u)) return RPIM_E_ARG;
+  return penalty_launch(row_ptr, col_idx, K, precision, n_dof, fixed, ubar, n_fixed, factor, rhs, alpha_out,
+                        status_out, ws, s);
+}
+
+rpim_status launch_penalty_noalloc(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision,
+                                   int64_t n_dof, const int32_t* fixed, const double* ubar, int64_t n_fixed,
+                                   double factor, double* rhs, double* alpha_out, int32_t* status_out,
+                                   hipStream_t s) {
+  if (n_fixed > kNoallocMaxFixed) return RPIM_E_RANGE;
+  void* ws = nullptr;
+  if (rpim_status st = scratch_for_current_device(&ws)) return st;
   return penalty_launch(row_ptr, col_idx, K, precision, n_dof, fixed, ubar, n_fixed, factor, rhs, alpha_out,
                         status_out, ws, s);
 }

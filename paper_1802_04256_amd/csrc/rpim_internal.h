@@ -208,5 +208,9 @@ size_t penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed);
 rpim_status launch_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision, int64_t n_dof,
                            const int32_t* fixed, const double* ubar, int64_t n_fixed, double factor, double* rhs,
                            double* alpha_out, int32_t* status_out, void* ws, size_t ws_size, hipStream_t s);
+rpim_status launch_penalty_noalloc(const int64_t* row_ptr, const int32_t* col_idx, void* K, int precision,
+                                   int64_t n_dof, const int32_t* fixed, const double* ubar, int64_t n_fixed,
+                                   double factor, double* rhs, double* alpha_out, int32_t* status_out,
+                                   hipStream_t s);
 
 }  // namespace rpim
