@@ -60,39 +60,6 @@ def shape_traffic():
     return SHAPE_TRAFFIC["bytes_per_step"] if h.hexdigest() == SHAPE_TRAFFIC["sources_sha256"] else None
 
 
-def csr_operator(row_ptr, col_idx, vals):
-    """x -> K x for a CSR matrix on the GPU, in float64 (float32 values are widened exactly)."""
-    import torch
-    n = row_ptr.numel() - 1
-    A = torch.sparse_csr_tensor(row_ptr, col_idx.to(torch.int64), vals.to(torch.float64), size=(n, n))
-    return lambda x: torch.mv(A, x)
-
-
-def pcg(A, b, dinv, rtol, maxit=50000):
-    """Jacobi-preconditioned conjugate gradients; returns (x, iterations, relative residual)."""
-    import torch
-    x = torch.zeros_like(b)
-    r = b.clone()
-    z = dinv * r
-    p = z.clone()
-    rz = torch.dot(r, z)
-    bn = float(torch.linalg.norm(b))
-    it, rel = 0, 1.0
-    for it in range(1, maxit + 1):
-        Ap = A(p)
-        alpha = rz / torch.dot(p, Ap)
-        x += alpha * p
-        r -= alpha * Ap
-        rel = float(torch.linalg.norm(r)) / bn
-        if rel <= rtol:
-            break
-        z = dinv * r
-        rz_new = torch.dot(r, z)
-        p = z + (rz_new / rz) * p
-        rz = rz_new
-    return x, it, rel
-
-
 def displacement_error(prob, row_ptr, col_idx, K64, K32, factor=1e8):
     """Relative displacement error of the mixed-precision K after a solve.
 
@@ -100,7 +67,8 @@ def displacement_error(prob, row_ptr, col_idx, K64, K32, factor=1e8):
     downward force on every node of the top surface.  u64 solves K64 u = f;
     since K32 u32 = f, u32 - u64 = K32^-1 (K64 - K32) u64 exactly, which is
     solved directly (its accuracy then does not depend on how far u64 is
-    converged).  K64 and K32 are modified in place by the penalty update."""
+    converged).  Both solves are the library's Jacobi-preconditioned CG on the
+    GPU.  K64 and K32 are modified in place by the penalty update."""
     import numpy as np
     import torch
     import paper_1802_04256_amd as rp
@@ -113,24 +81,46 @@ def displacement_error(prob, row_ptr, col_idx, K64, K32, factor=1e8):
     top = np.where(X[:, 2] == X[:, 2].max())[0]
     f = torch.zeros(3 * prob.n_nodes, dtype=torch.float64, device=dev)
     f[torch.from_numpy(3 * top + 2).to(dev)] = -1.0
-    rows = torch.repeat_interleave(torch.arange(3 * prob.n_nodes, device=dev), torch.diff(row_ptr))
-    diag = torch.zeros_like(f).index_add_(0, rows, torch.where(rows == col_idx.long(), K64, 0.0))
-    del rows
-    A64 = csr_operator(row_ptr, col_idx, K64)
-    A32 = csr_operator(row_ptr, col_idx, K32)
-    u64, it64, res64 = pcg(A64, f, 1.0 / diag, 1e-10)
-    d = A64(u64) - A32(u64)
-    du, it32, res32 = pcg(A32, d, 1.0 / diag, 1e-6)
+    t0 = time.perf_counter()
+    u64, it64, res64 = rp.solve_pcg(row_ptr, col_idx, K64, f, rtol=1e-10)
+    t_solve = time.perf_counter() - t0
+    n = 3 * prob.n_nodes
+    A64 = torch.sparse_csr_tensor(row_ptr, col_idx.long(), K64, size=(n, n))
+    A32 = torch.sparse_csr_tensor(row_ptr, col_idx.long(), K32.double(), size=(n, n))
+    d = torch.mv(A64, u64) - torch.mv(A32, u64)
+    del A64, A32
+    du, it32, res32 = rp.solve_pcg(row_ptr, col_idx, K32, d, rtol=1e-6)
     return {"u_rel_err": float(torch.linalg.norm(du) / torch.linalg.norm(u64)), "cg_iters": [it64, it32],
-            "cg_rel_residual": [res64, res32],
-            "load": "unit downward force on each top-surface node; base fixed by penalty 1e8 x max diag"}
+            "cg_rel_residual": [res64, res32], "solve_s": t_solve,
+            "load": "unit downward force on each top-surface node; base fixed by penalty 1e8 x max diag",
+            "solver": "rpim_solve_pcg (Jacobi-preconditioned CG, FP64 vectors)"}
 
 
-def batched_leg(plain_fp64_gp_s):
-    """64 independent jittered slopes (log-uniform 1k-30k nodes) in one plan, launch configuration tuned on
-    it: one HIP graph holding the whole mixed-precision assembly (pair table, one launch per support-size
-    bucket, row gather), replayed; the same batch assembled eagerly in FP64 beside it."""
+def graph_timing(fn, reps=5):
+    """Capture fn once in a HIP graph (after an eager call), replay it reps times; median, min, max in seconds."""
     import numpy as np
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - a)
+    del g
+    return float(np.median(ts)), float(min(ts)), float(max(ts))
+
+
+def batched_leg():
+    """64 independent jittered slopes (log-uniform 1k-30k nodes) in one plan, launch configuration tuned on
+    it: the whole assembly (pair table, one launch per support-size bucket, row gather) captured in one HIP
+    graph and replayed, in mixed precision and in FP64 on the same batch and in the same launch mode."""
     import torch
 
     import paper_1802_04256_amd as rp
@@ -144,55 +134,91 @@ def batched_leg(plain_fp64_gp_s):
     X = torch.from_numpy(prob.node_xyz).to(dev)
     E = torch.from_numpy(prob.cell_E).to(dev)
     K32 = torch.empty(plan.nnz, dtype=torch.float32, device=dev)
-    tuned = plan.autotune(X, E, prob.nu, rp.MIXED, out=K32)
-    plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
-    torch.cuda.synchronize()
-    plan.status()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
-
-    def timed(fn, reps=3):
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - a)
-        return float(np.median(ts))
-    t_graph = timed(graph.replay)
-    del graph
     K64 = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
-    plan.autotune(X, E, prob.nu, rp.FP64, out=K64)
-    plan.assemble(X, E, prob.nu, rp.FP64, out=K64)
-    t_fp64 = timed(lambda: plan.assemble(X, E, prob.nu, rp.FP64, out=K64))
-    plan.assemble(X, E, prob.nu, rp.MIXED, out=K32)
-    err = float(torch.linalg.norm(K32.double() - K64) / torch.linalg.norm(K64))
+    tuned = {"mixed": plan.autotune(X, E, prob.nu, rp.MIXED, out=K32)["gather_waves"],
+             "fp64": plan.autotune(X, E, prob.nu, rp.FP64, out=K64)["gather_waves"]}
+    t32 = graph_timing(lambda: plan.assemble(X, E, prob.nu, rp.MIXED, out=K32))
+    t64 = graph_timing(lambda: plan.assemble(X, E, prob.nu, rp.FP64, out=K64))
     plan.status()
+    err = float(torch.linalg.norm(K32.double() - K64) / torch.linalg.norm(K64))
     res = {"workload": "64 jittered slopes, log-uniform 1k-30k nodes (seed 4), lognormal E, one block-diagonal plan",
            "n_models": prob.n_models, "n_nodes": prob.n_nodes, "n_gp": prob.n_gp, "nnz": info["nnz"],
-           "sum_n": info["sum_n"], "buckets": info["n_buckets"],
-           "ms": {"mixed_graph": t_graph * 1e3, "fp64_eager": t_fp64 * 1e3},
-           "gp_per_s": {"mixed_graph": prob.n_gp / t_graph, "fp64_eager": prob.n_gp / t_fp64},
-           "mixed_rel_fro_err": err, "gather_waves_mixed": tuned["gather_waves"]}
-    if plain_fp64_gp_s:
-        res["mixed_graph_vs_plain_fp64_slope"] = res["gp_per_s"]["mixed_graph"] / plain_fp64_gp_s
-    log(f"batched: mixed graph {t_graph * 1e3:.1f} ms, fp64 {t_fp64 * 1e3:.1f} ms, err {err:.2e}")
+           "sum_n": info["sum_n"], "buckets": info["n_buckets"], "launch": "one HIP graph per precision, replayed",
+           "ms": {"mixed": t32[0] * 1e3, "fp64": t64[0] * 1e3},
+           "ms_min_max": {"mixed": [t32[1] * 1e3, t32[2] * 1e3], "fp64": [t64[1] * 1e3, t64[2] * 1e3]},
+           "gp_per_s": {"mixed": prob.n_gp / t32[0], "fp64": prob.n_gp / t64[0]},
+           "mixed_vs_fp64_same_batch": t64[0] / t32[0],
+           "mixed_rel_fro_err": err, "gather_waves": tuned}
+    log(f"batched: mixed {t32[0] * 1e3:.1f} ms [{t32[1] * 1e3:.1f}, {t32[2] * 1e3:.1f}], fp64 {t64[0] * 1e3:.1f} ms "
+        f"[{t64[1] * 1e3:.1f}, {t64[2] * 1e3:.1f}], err {err:.2e}")
     return res
 
 
-def cpu_baseline(prob, n_sample, n_vec=8):
-    """Oracle (serial, one core) on the first n_sample Gauss points of the workload:
-    pattern, FP64 assembly, penalty and adjoint, scaled to Gauss points per second."""
+def large_leg():
+    """The 3-layer slope at 250k nodes (100 x 50 x 50 m, 262,701 nodes, 6,750,000 Gauss points): assembly
+    throughput in FP64 and mixed precision (HIP graph replays), the mixed K error, and the displacement
+    error of the mixed K after a GPU solve."""
+    import torch
+
+    import paper_1802_04256_amd as rp
+    import workloads as W
+    dev = torch.device("cuda:0")
+    prob = W.named("slope_large")
+    log(f"large: nodes={prob.n_nodes} gps={prob.n_gp}")
+    plan = rp.Plan.from_problem(prob, device=dev)
+    t0 = time.perf_counter()
+    plan.build_pattern()
+    t_pat = time.perf_counter() - t0
+    info = plan.info()
+    X = torch.from_numpy(prob.node_xyz).to(dev)
+    E = torch.from_numpy(prob.cell_E).to(dev)
+    K32 = torch.empty(plan.nnz, dtype=torch.float32, device=dev)
+    K64 = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+    plan.autotune(X, E, prob.nu, rp.MIXED, out=K32)
+    plan.autotune(X, E, prob.nu, rp.FP64, out=K64)
+    t32 = graph_timing(lambda: plan.assemble(X, E, prob.nu, rp.MIXED, out=K32), reps=3)
+    t64 = graph_timing(lambda: plan.assemble(X, E, prob.nu, rp.FP64, out=K64), reps=3)
+    plan.status()
+    err = float(torch.linalg.norm(K32.double() - K64) / torch.linalg.norm(K64))
+    log(f"large: mixed {t32[0] * 1e3:.1f} ms, fp64 {t64[0] * 1e3:.1f} ms, K err {err:.2e}; solving ...")
+    disp = displacement_error(prob, plan.row_ptr, plan.col_idx, K64, K32)
+    log(f"large: displacement error {disp['u_rel_err']:.2e} (CG iterations {disp['cg_iters']})")
+    return {"workload": "3-layer jittered slope 100x50x50 m (E = 300 / 80 / 20 MPa), 262,701 nodes, 6,750,000 "
+                        "Gauss points", "n_gp": prob.n_gp, "nnz": info["nnz"], "sum_n": info["sum_n"],
+            "pattern_s": t_pat, "ms": {"mixed": t32[0] * 1e3, "fp64": t64[0] * 1e3},
+            "ms_min_max": {"mixed": [t32[1] * 1e3, t32[2] * 1e3], "fp64": [t64[1] * 1e3, t64[2] * 1e3]},
+            "gp_per_s": {"mixed": prob.n_gp / t32[0], "fp64": prob.n_gp / t64[0]},
+            "mixed_vs_fp64": t64[0] / t32[0], "mixed_rel_fro_err": err, "mixed_displacement": disp}
+
+
+def host_info():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_baseline(prob, cell_stride, n_vec=8):
+    """Oracle (serial, one core) on the Gauss points of every cell_stride-th cell of the workload,
+    spread over the whole domain: support search, pattern, FP64 assembly and adjoint, scaled to Gauss
+    points per second."""
     import numpy as np
 
     import oracle
     import workloads as W
-    sub = W.Problem(name="sample", node_xyz=prob.node_xyz, gp_xyz=prob.gp_xyz[:n_sample],
-                    gp_wdet=prob.gp_wdet[:n_sample], gp_cell=prob.gp_cell[:n_sample], cell_E=prob.cell_E,
-                    nu=prob.nu, support_radius=prob.support_radius, alpha_c=prob.alpha_c, d_c=prob.d_c,
-                    q=prob.q)
+    cells = np.arange(0, prob.n_cells, cell_stride)
+    gps = np.nonzero(np.isin(prob.gp_cell, cells))[0]
+    sub = W.Problem(name="sample", node_xyz=prob.node_xyz, gp_xyz=prob.gp_xyz[gps], gp_wdet=prob.gp_wdet[gps],
+                    gp_cell=prob.gp_cell[gps], cell_E=prob.cell_E, nu=prob.nu,
+                    support_radius=prob.support_radius, alpha_c=prob.alpha_c, d_c=prob.d_c, q=prob.q)
     oracle.lib()
     t0 = time.perf_counter()
     m = oracle.OracleModel(sub)
@@ -204,10 +230,13 @@ def cpu_baseline(prob, n_sample, n_vec=8):
     Kb = 0.5 * np.einsum("vi,vi->i", V[:, rows], V[:, ci])
     m.backward(Kb)
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "GP/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample} Gauss points ({n_sample // 27} cells) of the same slope: "
-                      f"oracle support search + pattern + FP64 assembly + adjoint, {dt:.1f} s serial (the penalty "
-                      f"update, O(dofs), is left out: nodes outside the sample have empty rows)"}
+    gp_ptr, _ = m.support()
+    n = np.diff(gp_ptr)
+    return {"value": len(gps) / dt, "unit": "GP/s", "cores": 1, "kind": "oracle", **host_info(),
+            "sample": f"the {len(gps)} Gauss points of every {cell_stride}th cell ({len(cells)} cells spread over the "
+                      f"slope; mean support {n.mean():.1f} nodes against {prob.meta.get('mean_support', 'n/a')} over "
+                      f"the whole slope): oracle support search + pattern + FP64 assembly + adjoint, {dt:.1f} s "
+                      f"serial on one core (the O(dofs) penalty update is left out)"}
 
 
 def main():
@@ -215,10 +244,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=2700, help="Gauss points in the oracle's timed sample")
+    ap.add_argument("--cpu-cell-stride", type=int, default=157,
+                    help="the oracle's timed sample: the Gauss points of every N-th cell")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the assembly-only / mixed measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-model batched assembly")
+    ap.add_argument("--no-large", action="store_true", help="skip the 250k-node slope")
+    ap.add_argument("--solver-probe", default="", metavar="KINDS",
+                    help="profiling aid: one FP64 assembly of the workload per solver kernel in this comma-separated "
+                         "list (window, panel, lds), then exit without timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="before the steps, run one device fill and one device copy of this many MiB "
                          "(a known-size reference for the HBM byte counters of a profiler)")
@@ -248,6 +282,15 @@ def main():
     info = plan.info()
     log(f"pattern: nnz={info['nnz']} sum_n={info['sum_n']} n={info['min_n']}..{info['max_n']} "
         f"buckets={info['n_buckets']}")
+    if args.solver_probe:
+        Kp = torch.empty(plan.nnz, dtype=torch.float64, device=dev)
+        for kind in args.solver_probe.split(","):
+            plan.set_solver(kind)
+            plan.assemble(X, E, prob.nu, rp.FP64, out=Kp)
+            torch.cuda.synchronize()
+            log(f"solver probe: {kind} assembly done")
+        plan.status()
+        return
     # probe-vector adjoint seed on the pattern: dL/dK_ij = 0.5 sum_v v_i v_j
     V = torch.from_numpy(W.probe_vectors(3 * prob.n_nodes, 8, 5)).to(dev)
     rows = torch.repeat_interleave(torch.arange(3 * prob.n_nodes, device=dev), torch.diff(row_ptr))
@@ -372,11 +415,14 @@ def main():
             f"bwd {t_bwd * 1e3:.2f} ms, bwd/fwd {out['bwd_fwd']:.2f}")
 
     if not args.no_extras and not args.no_batched:
-        out["batched"] = batched_leg(out.get("assemble_gp_per_s", {}).get("fp64"))
+        out["batched"] = batched_leg()
+    if not args.no_extras and not args.no_large:
+        out["large"] = large_leg()
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_sample)
+        prob.meta["mean_support"] = round(float(info["sum_n"]) / prob.n_gp, 1)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_cell_stride)
         log(f"cpu baseline {out['cpu_baseline']['value']:.1f} GP/s")
     print(json.dumps(out), flush=True)
 

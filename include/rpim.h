@@ -52,7 +52,8 @@ typedef enum {
   RPIM_E_SINGULAR = -5, /* |u_kk| <= N * eps * max|G| during the LU             */
   RPIM_E_RANGE = -6,    /* a size exceeds a documented limit                    */
   RPIM_E_POW = -7,      /* a power could not be rounded correctly (never seen)  */
-  RPIM_E_STATE = -8     /* call order violated (e.g. backward before assemble)  */
+  RPIM_E_STATE = -8,    /* call order violated (e.g. backward before assemble)  */
+  RPIM_E_CONVERGENCE = -9 /* an iteration limit was reached before its tolerance */
 } rpim_status;
 
 typedef enum {
@@ -178,6 +179,30 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
                                   double* alpha, int32_t* status, void* workspace, size_t workspace_bytes,
                                   void* stream);
 
+/* Stage 3: solve K x = rhs (GeoMFree3D Sec. 2, stage 3: the assembled sparse
+ * system is solved on the GPU) by conjugate gradients with the Jacobi
+ * (diagonal) preconditioner; K symmetric positive definite, e.g. an assembled
+ * stiffness after rpim_apply_penalty_bc.
+ *   row_ptr int64[n_dof + 1], col_idx int32[nnz] (sorted per row, every row
+ *   with a positive diagonal), K_vals double or float per `precision` (float
+ *   values are widened exactly); rhs double[n_dof]; x double[n_dof], the
+ *   initial guess on entry and the solution on return.
+ *   Stops when |rhs - K x| <= rtol |rhs| (2-norms) or after max_iter
+ *   iterations.  *iterations and *rel_residual (host, may be NULL) receive the
+ *   count and |rhs - K x| / |rhs| of the recursively updated residual.
+ *   workspace: caller-owned device memory of rpim_pcg_workspace_bytes(n_dof)
+ *   bytes, 256-byte aligned.
+ * All vector arithmetic is FP64 and every reduction has a fixed order, so a
+ * solve is deterministic.  Synchronous: the host tests convergence every 32
+ * iterations.  Returns RPIM_E_CONVERGENCE when max_iter is reached first,
+ * RPIM_E_SINGULAR when a diagonal is not positive or p.Kp <= 0 (x then holds
+ * the last iterate), RPIM_E_ARG for bad arguments. */
+size_t rpim_pcg_workspace_bytes(int64_t n_dof);
+rpim_status rpim_solve_pcg(const int64_t* row_ptr, const int32_t* col_idx, const void* K_vals, int precision,
+                           int64_t n_dof, const double* rhs, double* x, double rtol, int64_t max_iter,
+                           void* workspace, size_t workspace_bytes, int64_t* iterations, double* rel_residual,
+                           void* stream);
+
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): rpim_apply_penalty_bc
  * with the library's own device scratch in place of the workspace; the same
@@ -194,13 +219,17 @@ rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t*
                                           double* alpha, int32_t* status, void* stream);
 
 /* Launch-configuration tuning (synchronous).  Kept LU factors are invalidated.
- * Evaluates the pair table and the moment-matrix solves once, then times the row gather of `precision` with 2,
- * 3 and 4 waves per node row on this plan's own data and keeps the fastest for
- * later rpim_assemble calls with that precision (each configuration computes
- * the same bits; only speed differs).  K_vals (nnz values of the precision's
- * type) serves as scratch and is overwritten.  It also times each
- * support-size bucket's solver launch, for the report only.  `out` may be
- * NULL.  Supports and pattern must be built (RPIM_E_STATE otherwise). */
+ * For every support-size bucket it times the moment-matrix solver kernels
+ * that can hold the bucket (RPIM_SOLVER_WINDOW, RPIM_SOLVER_PANEL; the LDS
+ * kernel beyond them) and keeps the fastest for the bucket; then it times the
+ * row gather of `precision` with 2, 3 and 4 waves per node row and keeps the
+ * fastest.  Every configuration computes the same bits; only speed differs.
+ * K_vals (nnz values of the precision's type) serves as scratch and is
+ * overwritten.  The choices go to a process-wide cache keyed by (GPU
+ * architecture, precision, bucket size) and (architecture, precision); when
+ * the cache already holds every choice this plan needs, they are applied and
+ * nothing is timed (from_cache = 1).  `out` may be NULL.  Supports and pattern
+ * must be built (RPIM_E_STATE otherwise). */
 #define RPIM_TUNING_MAX_BUCKETS 32
 typedef struct {
   int32_t gather_waves;                          /* chosen: 2, 3 or 4              */
@@ -208,10 +237,20 @@ typedef struct {
   int32_t n_buckets;                             /* buckets reported (<= 32)       */
   int32_t bucket_nmax[RPIM_TUNING_MAX_BUCKETS];  /* padded size N of each bucket   */
   int64_t bucket_points[RPIM_TUNING_MAX_BUCKETS];
-  float bucket_ms[RPIM_TUNING_MAX_BUCKETS];      /* solver launch time             */
+  float bucket_ms[RPIM_TUNING_MAX_BUCKETS];      /* solver time, chosen kernel     */
+  int32_t bucket_solver[RPIM_TUNING_MAX_BUCKETS];   /* chosen RPIM_SOLVER_*        */
+  float bucket_ms_window[RPIM_TUNING_MAX_BUCKETS];  /* each candidate (-1: not run) */
+  float bucket_ms_panel[RPIM_TUNING_MAX_BUCKETS];
+  int32_t from_cache;                            /* 1: choices from the cache      */
 } rpim_tuning;
 rpim_status rpim_autotune(rpim_plan* plan, const double* node_xyz, const double* cell_E, double nu, int precision,
                           void* K_vals, void* stream, rpim_tuning* out);
+/* The tuning cache as text lines "arch precision what nmax value" (what =
+ * solver or gather).  Loading adds to the cache (RPIM_E_ARG for an unreadable
+ * file or a malformed line); clearing empties it. */
+rpim_status rpim_tuning_cache_save(const char* path);
+rpim_status rpim_tuning_cache_load(const char* path);
+void rpim_tuning_cache_clear(void);
 /* Set the row-gather configuration (2, 3 or 4 waves per node row) for
  * `precision` by hand, as rpim_autotune would; RPIM_E_ARG otherwise. */
 rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
@@ -221,10 +260,13 @@ rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
  * (the elimination order of the arithmetic contract); only speed differs.
  *   RPIM_SOLVER_AUTO   the library's choice (default)
  *   RPIM_SOLVER_LDS    the whole augmented matrix in LDS (any size up to 136)
- *   RPIM_SOLVER_WINDOW one matrix row per thread in registers (N <= 104)
- * Buckets a kernel cannot hold fall back to the LDS kernel.  RPIM_E_ARG for
- * an unknown kind or nmax outside [0, 136]. */
-enum { RPIM_SOLVER_AUTO = 0, RPIM_SOLVER_LDS = 1, RPIM_SOLVER_WINDOW = 2 };
+ *   RPIM_SOLVER_WINDOW one matrix row per thread in registers, eliminated one
+ *                      pivot step at a time (N <= 104)
+ *   RPIM_SOLVER_PANEL  rows in registers, blocked elimination: sixteen pivot
+ *                      steps on a panel, then one trailing update (N <= 96)
+ * Buckets a kernel cannot hold fall back to the window kernel, then to the
+ * LDS kernel.  RPIM_E_ARG for an unknown kind or nmax outside [0, 136]. */
+enum { RPIM_SOLVER_AUTO = 0, RPIM_SOLVER_LDS = 1, RPIM_SOLVER_WINDOW = 2, RPIM_SOLVER_PANEL = 3 };
 rpim_status rpim_set_solver(rpim_plan* plan, int nmax, int kind);
 
 /* Identifier of the LU factors the plan currently keeps for the backward: a

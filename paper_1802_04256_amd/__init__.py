@@ -12,7 +12,8 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "assemble", "apply_penalty_bc", "pow_cr", "RpimError", "library_path", "FP64", "MIXED"]
+__all__ = ["Plan", "assemble", "apply_penalty_bc", "solve_pcg", "pow_cr", "RpimError", "library_path", "FP64",
+           "MIXED"]
 
 FP64, MIXED = 0, 1
 PENALTY_NOALLOC_MAX_FIXED = 1 << 18  # RPIM_PENALTY_NOALLOC_MAX_FIXED in rpim.h
@@ -20,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "librpim.so")
 
 _STATUS = {0: "RPIM_OK", -1: "RPIM_E_ARG", -2: "RPIM_E_NOMEM", -3: "RPIM_E_HIP", -4: "RPIM_E_SUPPORT",
-           -5: "RPIM_E_SINGULAR", -6: "RPIM_E_RANGE", -7: "RPIM_E_POW", -8: "RPIM_E_STATE"}
+           -5: "RPIM_E_SINGULAR", -6: "RPIM_E_RANGE", -7: "RPIM_E_POW", -8: "RPIM_E_STATE",
+           -9: "RPIM_E_CONVERGENCE"}
 
 
 class RpimError(RuntimeError):
@@ -43,7 +45,9 @@ _TUNING_MAX = 32
 class _Tuning(C.Structure):
     _fields_ = [("gather_waves", C.c_int32), ("gather_ms", C.c_float * 3), ("n_buckets", C.c_int32),
                 ("bucket_nmax", C.c_int32 * _TUNING_MAX), ("bucket_points", C.c_int64 * _TUNING_MAX),
-                ("bucket_ms", C.c_float * _TUNING_MAX)]
+                ("bucket_ms", C.c_float * _TUNING_MAX), ("bucket_solver", C.c_int32 * _TUNING_MAX),
+                ("bucket_ms_window", C.c_float * _TUNING_MAX), ("bucket_ms_panel", C.c_float * _TUNING_MAX),
+                ("from_cache", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -74,6 +78,10 @@ def lib():
         L.rpim_apply_penalty_bc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, vp, vp, vp, C.c_size_t, vp]
         L.rpim_apply_penalty_bc_noalloc.argtypes = [vp, vp, vp, i32, i64, vp, vp, i64, d, vp, vp, vp, vp]
         L.rpim_penalty_workspace_bytes.argtypes = [i64, i64]
+        L.rpim_pcg_workspace_bytes.argtypes = [i64]
+        L.rpim_pcg_workspace_bytes.restype = C.c_size_t
+        L.rpim_solve_pcg.argtypes = [vp, vp, vp, i32, i64, vp, vp, d, i64, vp, C.c_size_t, C.POINTER(i64),
+                                     C.POINTER(d), vp]
         L.rpim_penalty_workspace_bytes.restype = C.c_size_t
         L.rpim_get_status.argtypes = [vp, vp, C.POINTER(i64)]
         L.rpim_plan_info.argtypes = [vp, C.POINTER(_Info)]
@@ -86,6 +94,9 @@ def lib():
         L.rpim_autotune.argtypes = [vp, vp, vp, d, i32, vp, vp, C.POINTER(_Tuning)]
         L.rpim_set_gather_waves.argtypes = [vp, i32, i32]
         L.rpim_set_solver.argtypes = [vp, i32, i32]
+        L.rpim_tuning_cache_save.argtypes = [C.c_char_p]
+        L.rpim_tuning_cache_load.argtypes = [C.c_char_p]
+        L.rpim_tuning_cache_clear.restype = None
         L.rpim_factor_generation.argtypes = [vp, C.POINTER(i64)]
         L.rpim_plan_destroy.argtypes = [vp]
         L.rpim_plan_destroy.restype = None
@@ -94,7 +105,8 @@ def lib():
                   "rpim_apply_penalty_bc", "rpim_get_status", "rpim_plan_info", "rpim_get_support",
                   "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
                   "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves", "rpim_set_solver",
-                  "rpim_factor_generation", "rpim_apply_penalty_bc_noalloc"):
+                  "rpim_factor_generation", "rpim_apply_penalty_bc_noalloc",
+                  "rpim_solve_pcg", "rpim_tuning_cache_save", "rpim_tuning_cache_load"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -238,15 +250,18 @@ class Plan:
         _check(lib().rpim_autotune(self._h, _ptr(X), _ptr(E), float(nu), prec, _ptr(out), _stream(), C.byref(t)),
                "rpim_autotune")
         n = t.n_buckets
-        return {"gather_waves": t.gather_waves,
+        kinds = {v: k for k, v in self.SOLVERS.items()}
+        return {"gather_waves": t.gather_waves, "from_cache": bool(t.from_cache),
                 "gather_ms": {w: t.gather_ms[w - 2] for w in (2, 3, 4)},
-                "buckets": [{"nmax": t.bucket_nmax[i], "points": t.bucket_points[i], "ms": t.bucket_ms[i]}
+                "buckets": [{"nmax": t.bucket_nmax[i], "points": t.bucket_points[i], "ms": t.bucket_ms[i],
+                             "solver": kinds.get(t.bucket_solver[i], t.bucket_solver[i]),
+                             "ms_window": t.bucket_ms_window[i], "ms_panel": t.bucket_ms_panel[i]}
                             for i in range(n)]}
 
     def set_gather_waves(self, precision, waves: int):
         _check(lib().rpim_set_gather_waves(self._h, _precision(precision), int(waves)), "rpim_set_gather_waves")
 
-    SOLVERS = {"auto": 0, "lds": 1, "window": 2}
+    SOLVERS = {"auto": 0, "lds": 1, "window": 2, "panel": 3}
 
     def set_solver(self, kind, nmax: int = 0):
         """Moment-matrix solver kernel for the bucket of padded size nmax (0: all buckets)."""
@@ -342,6 +357,36 @@ def apply_penalty_bc(row_ptr, col_idx, K, fixed_dof, u_bar=None, factor=1e8, rhs
         raise RpimError(code, "rpim_apply_penalty_bc", "(fixed dofs not strictly ascending in range, or a "
                                                        "diagonal missing; K left unchanged)")
     return float(alpha.item())
+
+
+def tuning_cache(save=None, load=None, clear=False):
+    """Save the process-wide tuning cache to a file, load one into it, or clear it."""
+    if clear:
+        lib().rpim_tuning_cache_clear()
+    if load is not None:
+        _check(lib().rpim_tuning_cache_load(os.fsencode(load)), "rpim_tuning_cache_load")
+    if save is not None:
+        _check(lib().rpim_tuning_cache_save(os.fsencode(save)), "rpim_tuning_cache_save")
+
+
+def solve_pcg(row_ptr, col_idx, K, rhs, x0=None, rtol=1e-10, max_iter=200000, raise_on_error=True):
+    """Jacobi-preconditioned CG on the GPU for K x = rhs (K float64 or float32 on the CSR pattern).
+
+    Returns (x, iterations, relative residual).  With raise_on_error=False a breakdown or the iteration
+    limit returns the last iterate instead of raising."""
+    torch = _torch()
+    prec = FP64 if K.dtype == torch.float64 else MIXED
+    n = int(row_ptr.numel() - 1)
+    b = _dev(rhs, torch.float64, K.device)
+    x = torch.zeros(n, dtype=torch.float64, device=K.device) if x0 is None else _dev(x0, torch.float64, K.device).clone()
+    nbytes = lib().rpim_pcg_workspace_bytes(n)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=K.device)
+    iters, rel = C.c_int64(), C.c_double()
+    st = lib().rpim_solve_pcg(_ptr(row_ptr), _ptr(col_idx), _ptr(K), prec, n, _ptr(b), _ptr(x), float(rtol),
+                              int(max_iter), _ptr(ws), nbytes, C.byref(iters), C.byref(rel), _stream())
+    if st != 0 and raise_on_error:
+        raise RpimError(st, "rpim_solve_pcg", f"(after {iters.value} iterations, relative residual {rel.value:.3e})")
+    return x, iters.value, rel.value
 
 
 def pow_cr(x, q):

@@ -96,9 +96,9 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
   const int N = n + 4, W = N + 3;
   double* A = smem;
   int* S = (int*)(A + (size_t)N * ld);
-  int* pv = S + n;  // original row now at each position
+  int* pv = S + n;  // pivot position of each step, before its interchange
+  double* F = keep ? lu + lu_off[g] : nullptr;  // packed factors: multipliers by position, then U
   for (int i = tid; i < n; i += kThreads) S[i] = gp_nbr[b0 + i];
-  for (int i = tid; i < N; i += kThreads) pv[i] = i;
   for (int i = tid; i < N * ld; i += kThreads) A[i] = 0.0;
   if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
   __syncthreads();
@@ -155,11 +155,7 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
     int p;
     argmax_pair(v, r, red_v, red_r, &best, &p);
     if (!(best > tiny)) { singular = true; break; }
-    if (tid == 0 && p != k) {
-      const int t = pv[k];
-      pv[k] = pv[p];
-      pv[p] = t;
-    }
+    if (tid == 0) pv[k] = p;  // the pivot's position before the interchange
     if (p != k)
       for (int c = tid; c < W; c += kThreads) {
         const double t = A[k * ld + c];
@@ -168,7 +164,11 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
       }
     __syncthreads();
     const double piv = A[k * ld + k];
-    for (int i = k + 1 + tid; i < N; i += kThreads) A[i * ld + k] = A[i * ld + k] / piv;
+    for (int i = k + 1 + tid; i < N; i += kThreads) {
+      const double l = A[i * ld + k] / piv;
+      A[i * ld + k] = l;
+      if (F) F[(int64_t)k * N + i] = l;  // multiplier of the row now at position i
+    }
     __syncthreads();
     const int m = N - k - 1, wc = W - k - 1;
     for (int idx = tid; idx < m * wc; idx += kThreads) {
@@ -197,12 +197,9 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
     if (dphi32) dphi32[3 * (b0 + a) + k] = (float)A[a * ld + N + k];
   }
   if (keep) {
-    double* L = lu + lu_off[g];  // multipliers by (step, original row), then U rows by position
-    double* U = L + (int64_t)N * N;
     for (int idx = tid; idx < N * N; idx += kThreads) {
       const int r = idx / N, c = idx - r * N;  // position r, column c
-      if (c < r) L[(int64_t)c * N + pv[r]] = A[r * ld + c];
-      else U[(int64_t)c * N + r] = A[r * ld + c];
+      if (c >= r) F[(int64_t)c * N + r] = A[r * ld + c];
     }
     const int64_t o = b0 + 4 * g;
     for (int i = tid; i < N; i += kThreads) piv_out[o + i] = pv[i];
@@ -214,14 +211,19 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 }
 
 // ---- row gather: one workgroup per node row I --------------------------------
-// acc[pos][9] over the row's column blocks (pos = rank of J in row I).  The
-// row's columns are cut into GW ranges of node ids and wave w owns
-// the slots of its range, so no slot is touched by two waves.  Each wave walks
-// the row's Gauss points in ascending g; since supports are sorted, the part
-// of a point's support inside the wave's range is a contiguous run, found with
-// two ballots, and its entries go one per lane, each lane adding all nine
-// entries of its 3x3 block.  A wave's LDS accesses execute in program order,
-// so every slot receives its contributions in ascending g without barriers.
+// K is symmetric bit for bit: each point's block (J, I) is the transpose of its
+// block (I, J) with every entry rounded identically (the contract's products
+// commute), and both entries sum the same points in the same order.  So row I
+// assembles only its blocks J >= I and also writes each one, transposed, into
+// row J: half the work and half the LDS of a full row.
+// acc[s][9] over the row's upper blocks (s = rank of J in row I minus the rank
+// of I).  Those columns are cut into GW ranges of node ids and wave w owns the
+// slots of its range, so no slot is touched by two waves.  Each wave walks the
+// row's Gauss points in ascending g; since supports are sorted, the part of a
+// point's support inside the wave's range is a contiguous run, found with two
+// ballots, and its entries go one per lane, each lane adding all nine entries
+// of its 3x3 block.  A wave's LDS accesses execute in program order, so every
+// slot receives its contributions in ascending g without barriers.
 template <bool kMixed, int GW>
 __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
                                                               const int32_t* row_lo,
@@ -230,28 +232,33 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
                                                               const int64_t* gp_ptr, const int32_t* gp_nbr,
                                                               const void* dphi_any, const double* wdet,
                                                               const int32_t* gp_cell, const double* E, double lam,
-                                                              double mu, void* Kout, int64_t n_rows) {
+                                                              double mu, void* Kout) {
   extern __shared__ double smem[];
   // gradients: FP64, or rounded to float by the solver for the mixed path
   using T = typename std::conditional<kMixed, float, double>::type;
   const T* dphi = static_cast<const T*>(dphi_any);
-  const int64_t I = xcd_row(blockIdx.x, n_rows);
-  if (I >= n_rows) return;  // padding workgroup (uniform)
+  const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
-  double* acc = smem;                 // [L][9] double sums, or (sum, compensation) float pairs (mixed)
-  uint2* bm = (uint2*)(acc + 9 * L);  // row I's rank bitmap
+  if (L == 0) return;  // a node in no support has an empty row (uniform)
   const int tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const int lo_I = row_lo[I];
   const int64_t wb = rbm_off[I];
   const int nw = (int)(rbm_off[I + 1] - wb);
+  // rank of the diagonal block in row I; the upper blocks follow it
+  const int rI = (int)I - lo_I;
+  const uint2 wI = rbm[wb + (rI >> 5)];
+  const int pd = (int)wI.y + __popc(wI.x & ((1u << (rI & 31)) - 1u));
+  const int Lu = L - pd;
+  double* acc = smem;                  // [Lu][9] double sums, or (sum, compensation) float pairs (mixed)
+  uint2* bm = (uint2*)(acc + 9 * Lu);  // row I's rank bitmap
   constexpr int kThreadsG = 64 * GW;
   for (int i = tid; i < nw; i += kThreadsG) bm[i] = rbm[wb + i];
-  for (int i = tid; i < 9 * L; i += kThreadsG) acc[i] = 0.0;  // +0 sums and compensations
-  // this wave's columns: node ids in [thr_lo, thr_hi)
-  const int32_t thr_lo = w == 0 ? INT_MIN : blk_col[rb + (int64_t)w * L / GW];
-  const int32_t thr_hi = w + 1 == GW ? INT_MAX : blk_col[rb + (int64_t)(w + 1) * L / GW];
+  for (int i = tid; i < 9 * Lu; i += kThreadsG) acc[i] = 0.0;  // +0 sums and compensations
+  // this wave's columns: node ids in [thr_lo, thr_hi), from I upwards
+  const int32_t thr_lo = w == 0 ? (int32_t)I : blk_col[rb + pd + (int64_t)w * Lu / GW];
+  const int32_t thr_hi = w + 1 == GW ? INT_MAX : blk_col[rb + pd + (int64_t)(w + 1) * Lu / GW];
   __syncthreads();
 
   // Software pipeline over the row's Gauss points: point metadata (scalar)
@@ -310,7 +317,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   auto accum = [&](int32_t J, const T (&pJ)[3], const T (&pI)[3], double lc, double mc) {
     const int r = J - lo_I;
     const uint2 wv = bm[r >> 5];
-    const int pos = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u));
+    const int pos = (int)wv.y + __popc(wv.x & ((1u << (r & 31)) - 1u)) - pd;  // upper slot
     if constexpr (!kMixed) {
       const double dot = __builtin_fma(pI[2], pJ[2], __builtin_fma(pI[1], pJ[1], pI[0] * pJ[0]));
       double m[3][3];
@@ -392,12 +399,30 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
     r_cur = r_nxt;
   }
   __syncthreads();
-  const int64_t base = 9 * rb;
-  for (int idx = tid; idx < 9 * L; idx += kThreadsG) {
-    const int pos = idx / 9, r = idx - 9 * pos, a = r / 3, be = r - 3 * a;
-    const int64_t o = base + 3 * (int64_t)a * L + 3 * pos + be;
-    if (!kMixed) ((double*)Kout)[o] = acc[idx];
-    else ((float*)Kout)[o] = reinterpret_cast<const float2*>(acc)[idx].x;  // the compensated sum
+  // row I: its upper blocks, three contiguous runs of 3 Lu entries (one per row alpha)
+  auto slot = [&](int i) -> T {
+    if constexpr (!kMixed) return acc[i];
+    else return reinterpret_cast<const float2*>(acc)[i].x;  // the compensated sum
+  };
+  T* K = static_cast<T*>(Kout);
+  const int64_t base = 9 * rb + 3 * (int64_t)pd;
+  for (int idx = tid; idx < 9 * Lu; idx += kThreadsG) {
+    const int a = idx / (3 * Lu), rem = idx - 3 * Lu * a, sl = rem / 3, be = rem - 3 * sl;
+    K[base + 3 * (int64_t)a * L + rem] = slot(9 * sl + 3 * a + be);
+  }
+  // row J > I: block (J, I) is block (I, J) transposed, at I's rank in row J
+  for (int sl = 1 + tid; sl < Lu; sl += kThreadsG) {
+    const int32_t J = blk_col[rb + pd + sl];
+    const int64_t bJ = blk_ptr[J];
+    const int64_t LJ = blk_ptr[J + 1] - bJ;
+    const int rJ = (int)I - row_lo[J];
+    const uint2 wJ = rbm[rbm_off[J] + (rJ >> 5)];
+    const int64_t pJ = (int64_t)wJ.y + __popc(wJ.x & ((1u << (rJ & 31)) - 1u));
+    const int64_t oJ = 9 * bJ + 3 * pJ;
+#pragma unroll
+    for (int be = 0; be < 3; ++be)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) K[oJ + 3 * be * LJ + a] = slot(9 * sl + 3 * a + be);
   }
 }
 
@@ -421,6 +446,8 @@ rpim_status launch_shape_bucket(rpim_plan* p, const Bucket& b, const double* X, 
   const double ac = p->alpha_c * p->d_c;
   const double C2 = ac * ac;
   const int kind = p->solver_kind[b.nmax / kBucketStep];
+  if (kind == RPIM_SOLVER_PANEL && b.nmax <= shape_panel_max())
+    return launch_shape_panel(p, b, X, C2, keep, dphi32, s);
   if (kind != RPIM_SOLVER_LDS && b.nmax <= shape_reg_max()) return launch_shape_reg(p, b, X, C2, keep, dphi32, s);
   const int N = b.nmax;
   const int ld = ((N + 3) | 1);  // odd row stride in doubles
@@ -445,12 +472,12 @@ rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32,
 template <bool kMixed, int GW>
 rpim_status launch_gather_t(rpim_plan* p, const double* E, double lam, double mu, void* K, size_t lds, hipStream_t s) {
   if (rpim_status st = raise_lds_limit((const void*)k_rowgather<kMixed, GW>, lds, p->device)) return st;
-  hipLaunchKernelGGL((k_rowgather<kMixed, GW>), dim3((unsigned)xcd_rows_grid(p->N)), dim3(64 * GW), lds, s,
+  hipLaunchKernelGGL((k_rowgather<kMixed, GW>), dim3((unsigned)p->N), dim3(64 * GW), lds, s,
                      (const int64_t*)p->blk_ptr, (const int32_t*)p->blk_col, (const int32_t*)p->row_lo,
                      (const int64_t*)p->rbm_off, (const uint2*)p->rbm, (const int64_t*)p->inv_ptr,
                      (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr,
                      kMixed ? (const void*)p->dphi32 : (const void*)p->dphi, (const double*)p->gp_wdet,
-                     (const int32_t*)p->gp_cell, E, lam, mu, K, p->N);
+                     (const int32_t*)p->gp_cell, E, lam, mu, K);
   RPIM_HIP(hipGetLastError());
   return RPIM_OK;
 }
@@ -463,8 +490,8 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   const double onem = 1.0 - 2.0 * nu;
   const double lam = nu / (onep * onem);
   const double mu = 1.0 / (2.0 * onep);
-  const int L = (int)p->max_row_blocks;
-  const size_t lds = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
+  const int Lu = (int)p->max_row_upper;
+  const size_t lds = sizeof(double) * 9 * (size_t)Lu + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds > 160 * 1024) return RPIM_E_RANGE;
   const int gw = gather_waves > 0 ? gather_waves : p->gather_waves[precision == RPIM_MIXED ? 1 : 0];
   if (precision == RPIM_FP64) {

@@ -69,11 +69,9 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
                                                  const int64_t* inv_ptr, const uint64_t* inv_key,
                                                  const int64_t* gp_ptr, const int32_t* gp_nbr, const double* dphi,
                                                  const double* wdet, const int32_t* gp_cell, const double* E,
-                                                 double lam, double mu, const double* M, double* pbar, double* dEs,
-                                                 int64_t n_rows) {
+                                                 double lam, double mu, const double* M, double* pbar, double* dEs) {
   extern __shared__ double smem[];
-  const int64_t I = xcd_row(blockIdx.x, n_rows);
-  if (I >= n_rows) return;  // padding workgroup (uniform)
+  const int64_t I = blockIdx.x;
   const int64_t rb = blk_ptr[I];
   const int L = (int)(blk_ptr[I + 1] - rb);
   double* Mrow = smem;                  // [L][9]  M_IJ blocks of row I
@@ -173,12 +171,13 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   int64_t* rwbS = (int64_t*)(xs + 3 * n);  // [n] rank-word offset of each support node's row
   int64_t* rbpS = rwbS + n;                // [n] pattern start of each support node's row
   int* S = (int*)(rbpS + n);      // [n]
-  int* rowat = S + n;             // [N] original row at each position
-  int* posf = rowat + N;          // [N] final position of each original row
-  int* rloS = posf + N;           // [n] window start of each support node's row
+  int* ppos = S + n;              // [N] position of each step's pivot before its interchange
+  int* rloS = ppos + N;           // [n] window start of each support node's row
   const int64_t o = b0 + 4 * g;
-  const double* Lm = lu + lu_off[g];      // multipliers [k][original row]
-  const double* U = Lm + (int64_t)N * N;  // U column-major by position
+  // packed factors, column-major F[c*N + p]: u_pc for p <= c; for p > c the
+  // multiplier of step c for the row at position p after that step's interchange
+  const double* Fm = lu + lu_off[g];
+  const double* U = Fm;
   for (int idx = tid; idx < 3 * N; idx += nT) gm[idx] = gam[3 * o + idx];
   for (int i = tid; i < n; i += nT) {
     const int32_t sidx = gp_nbr[b0 + i];
@@ -188,40 +187,55 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
     rbpS[i] = blk_ptr[sidx];
     for (int k = 0; k < 3; ++k) xs[3 * i + k] = X[3 * (int64_t)sidx + k];
   }
-  for (int i = tid; i < N; i += nT) rowat[i] = piv[o + i];
+  for (int i = tid; i < N; i += nT) ppos[i] = piv[o + i];
   if (tid < 3) xg[tid] = gp_xyz[3 * g + tid];
-  __syncthreads();
-  for (int i = tid; i < N; i += nT) posf[rowat[i]] = i;
   // right-hand side [Phibar_k; 0] of my original row
   const bool own = tid < N;
   double b[3] = {0.0, 0.0, 0.0};
   if (own && tid < n)
     for (int k = 0; k < 3; ++k) b[k] = pbar[3 * (b0 + tid) + k];
   __syncthreads();
-  const int my_posf = own ? posf[tid] : -1;
-  // forward substitution on original rows
-  // Factor entries are read PF steps ahead into registers (coalesced over the
-  // threads; addresses clamped into the point's factors so the loads need no
-  // branch), so each step's barrier does not wait on memory.
+  // Forward substitution on original rows, replaying the interchanges: thread r
+  // tracks the position of its row (the pivot of step k takes position k, the
+  // row that held k takes the pivot's old position).  Factor entries are read
+  // PF steps ahead; a second tracker replays the interchanges PF steps ahead of
+  // the first, so each entry is read at the position the row will hold then.
   constexpr int PF = 8;
-  const int trow = own ? tid : 0;
+  const auto interchange = [&](int k, int q) {  // position after step k of a row at q before it
+    const int pk = ppos[k];
+    return q == pk ? k : (q == k ? pk : q);
+  };
+  int pos = own ? tid : N;   // position before the current step
+  int posa = pos;            // position after the steps already prefetched
   double fcur[PF], fnxt[PF];
+  const auto fetch = [&](int k, int q) { return Fm[(int64_t)k * N + (q < N ? q : N - 1)]; };
 #pragma unroll
-  for (int j = 0; j < PF; ++j) fcur[j] = Lm[(int64_t)(j < N ? j : N - 1) * N + trow];
+  for (int j = 0; j < PF; ++j) {
+    if (j < N) {
+      posa = interchange(j, posa);
+      fcur[j] = fetch(j, posa);
+    }
+  }
   for (int k0 = 0; k0 < N; k0 += PF) {
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int kk = k0 + PF + j;
-      fnxt[j] = Lm[(int64_t)(kk < N ? kk : N - 1) * N + trow];
+      if (kk < N) {  // uniform
+        posa = interchange(kk, posa);
+        fnxt[j] = fetch(kk, posa);
+      }
     }
 #pragma unroll
     for (int j = 0; j < PF; ++j) {
       const int k = k0 + j;
       if (k < N) {  // uniform
-        if (own && my_posf == k)
+        const int after = interchange(k, pos);
+        if (own && after == k) {  // my row is the pivot of step k
           for (int c = 0; c < 3; ++c) y[c * N + k] = b[c];
+        }
+        pos = after;
         __syncthreads();
-        if (own && my_posf > k)
+        if (own && pos > k)
           for (int c = 0; c < 3; ++c) b[c] = __builtin_fma(-fcur[j], y[c * N + k], b[c]);
       }
     }
@@ -230,6 +244,7 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   }
   __syncthreads();
   // back substitution by position: thread p holds y_p; u_{p,k} read PF steps ahead
+  const int trow = own ? tid : 0;
   double yp[3] = {0.0, 0.0, 0.0};
   if (own)
     for (int j = 0; j < 3; ++j) yp[j] = y[j * N + tid];
@@ -411,18 +426,18 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   const size_t lds_rows = sizeof(double) * 9 * (size_t)L + sizeof(uint2) * (size_t)p->max_row_words;
   if (lds_rows > 160 * 1024) return RPIM_E_RANGE;
   if ((st = raise_lds_limit((const void*)k_bwd_rows, lds_rows, p->device)) != RPIM_OK) return st;
-  hipLaunchKernelGGL(k_bwd_rows, dim3((unsigned)xcd_rows_grid(p->N)), dim3(kT), lds_rows, s, (const int64_t*)p->blk_ptr,
+  hipLaunchKernelGGL(k_bwd_rows, dim3((unsigned)p->N), dim3(kT), lds_rows, s, (const int64_t*)p->blk_ptr,
                      (const int32_t*)p->row_lo, (const int64_t*)p->rbm_off, (const uint2*)p->rbm,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key,
                      (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, (const double*)p->dphi,
                      (const double*)p->gp_wdet, (const int32_t*)p->gp_cell, E, lam, mu, (const double*)p->msym,
-                     p->pbar, p->dEs, p->N);
+                     p->pbar, p->dEs);
   RPIM_HIP(hipGetLastError());
   phase_end(p, RPIM_PHASE_BWD_ROWS, s);
   phase_begin(p, RPIM_PHASE_BWD_GP, s);
   for (const Bucket& b : p->buckets) {
     const int N = b.nmax;
-    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(4 * N);
+    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(3 * N);
     const int threads = 64 * ((N + 63) / 64);  // whole waves, at least one thread per unknown
     if (threads > kT) return RPIM_E_RANGE;
     hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(threads), lds, s, (const int32_t*)p->gp_order, b.begin,

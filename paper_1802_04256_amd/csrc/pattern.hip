@@ -276,9 +276,11 @@ __global__ void __launch_bounds__(256) k_blocks_union(const int64_t* inv_ptr, co
 }
 
 // Expand row I's bitmap into its sorted columns and set each word's prefix
-// count (position of J in row I = prefix + popc(bits below J)).
+// count (position of J in row I = prefix + popc(bits below J)); upper[I] gets
+// the number of columns J >= I.
 __global__ void __launch_bounds__(256) k_blocks_fill(const int32_t* win_lo, const int64_t* blk_ptr, int32_t* blk_col,
-                                                     int32_t* blk_row, const int64_t* rbm_off, uint2* rbm) {
+                                                     int32_t* blk_row, const int64_t* rbm_off, uint2* rbm,
+                                                     int32_t* upper) {
   const int64_t I = blockIdx.x;
   const int lo = win_lo[I];
   const int64_t w_beg = rbm_off[I];
@@ -294,10 +296,13 @@ __global__ void __launch_bounds__(256) k_blocks_fill(const int32_t* win_lo, cons
   int pos = 0;
   for (int t = 0; t < (int)threadIdx.x; ++t) pos += part[t];
   const int64_t out = blk_ptr[I] + pos;
+  const int rI = (int)I - lo, wI = rI >> 5;
+  if (nw == 0 && threadIdx.x == 0) upper[I] = 0;  // empty row
   int k = 0;
   for (int i = w0; i < w1; ++i) {
     unsigned v = rbm[w_beg + i].x;
     rbm[w_beg + i].y = (unsigned)(pos + k);
+    if (i == wI) upper[I] = (int32_t)(blk_ptr[I + 1] - blk_ptr[I]) - (pos + k + __popc(v & ((1u << (rI & 31)) - 1u)));
     while (v) {
       const int bit = __ffs(v) - 1;
       v &= v - 1;
@@ -548,9 +553,14 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   for (int64_t i = 0; i < N; ++i) p->max_row_blocks = std::max<int64_t>(p->max_row_blocks, cnt_h[i]);
   RPIM_HIP(hipMalloc((void**)&p->blk_col, sizeof(int32_t) * nblk));
   RPIM_HIP(hipMalloc((void**)&p->blk_row, sizeof(int32_t) * nblk));
+  int32_t* upper = inv_cnt;  // reuse (size N): columns J >= I of each row
   hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)N), dim3(256), 0, s, (const int32_t*)win_lo,
-                     (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row, (const int64_t*)p->rbm_off, p->rbm);
+                     (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row, (const int64_t*)p->rbm_off, p->rbm, upper);
   RPIM_HIP(hipGetLastError());
+  RPIM_HIP(hipMemcpyAsync(cnt_h.data(), upper, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipStreamSynchronize(s));
+  p->max_row_upper = 0;
+  for (int64_t i = 0; i < N; ++i) p->max_row_upper = std::max<int64_t>(p->max_row_upper, cnt_h[i]);
 
   // buckets by padded moment-matrix size, and LU offsets (host, from gp_ptr)
   p->min_n = INT32_MAX;
@@ -563,7 +573,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     p->min_n = std::min(p->min_n, n);
     p->max_n = std::max(p->max_n, n);
     bcount[(n + 4 + kBucketStep - 1) / kBucketStep]++;
-    lu_off_h[g + 1] = lu_off_h[g] + 2 * (int64_t)(n + 4) * (n + 4);  // multipliers + U rows
+    lu_off_h[g + 1] = lu_off_h[g] + (int64_t)(n + 4) * (n + 4);  // packed multipliers and U
   }
   p->lu_doubles = lu_off_h[G];
   p->buckets.clear();

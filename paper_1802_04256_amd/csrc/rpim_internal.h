@@ -44,19 +44,6 @@ __device__ __forceinline__ int64_t block_pos(const int64_t* blk_ptr, const int32
   return blk_ptr[I] + (int64_t)w.y + __popc(w.x & ((1u << (r & 31)) - 1u));
 }
 
-// Row-major work over node rows, launched as 8 * ceil(n / 8) workgroups:
-// workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod 8),
-// so XCD x is given the contiguous rows [x * chunk, (x + 1) * chunk) in
-// ascending order.  Neighbouring rows share most of their Gauss points, so
-// this keeps those points' data in the L2 of the XCD that re-reads it.
-// Returns a row >= n for the padding workgroups.
-constexpr int kXcds = 8;
-__host__ __device__ __forceinline__ int64_t xcd_rows_grid(int64_t n) { return kXcds * ((n + kXcds - 1) / kXcds); }
-__device__ __forceinline__ int64_t xcd_row(int64_t b, int64_t n) {
-  const int64_t chunk = (n + kXcds - 1) / kXcds;
-  return (b % kXcds) * chunk + b / kXcds;
-}
-
 struct Bucket {
   int nmax;        // largest N = n + 4 in the bucket
   int64_t begin;   // range in gp_order
@@ -101,6 +88,7 @@ struct rpim_plan {
   int64_t rbm_words = 0;
   int32_t max_row_words = 0;
   int64_t max_row_blocks = 0;    // longest node-block row
+  int64_t max_row_upper = 0;     // most blocks J >= I in a row I
   int64_t max_inverse = 0;       // longest inverse list
   std::vector<rpim::Bucket> buckets;
   // solver kernel per bucket (index nmax / kBucketStep): RPIM_SOLVER_* from rpim.h
@@ -113,9 +101,10 @@ struct rpim_plan {
   float* dphi32 = nullptr;       // [sum_n][3] (mixed precision)
 
   // kept factors (keep_factors = 1)
-  // per point, 2 N^2 doubles at lu_off[g]: the multipliers column-major by original
-  // row (L[k*N + r] = multiplier of row r at step k), then U by position, column-major
-  // (U[c*N + p] = u_pc, c >= p); piv holds the original row pivoted at each step.
+  // per point, N^2 doubles at lu_off[g], column-major F[c*N + p]: for p <= c the
+  // U entry u_pc (rows by position), for p > c the multiplier applied at step c to
+  // the row that held position p after step c's interchange; piv[k] holds the
+  // position the pivot of step k held before that interchange (>= k).
   int64_t* lu_off = nullptr;     // [G+1]
   int64_t lu_doubles = 0;
   double* lu = nullptr;          // [lu_doubles]
@@ -197,11 +186,20 @@ int gather_waves_valid(int gw);
 int shape_reg_max();
 rpim_status launch_shape_reg(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, float* dphi32,
                              hipStream_t s);
+int shape_panel_max();
+rpim_status launch_shape_panel(rpim_plan* p, const Bucket& b, const double* X, double C2, int keep, float* dphi32,
+                               hipStream_t s);
 rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hipStream_t s);
 
 // --- backward.hip ------------------------------------------------------------
 rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, double nu,
                             const double* dK, double* dE, double* dX, hipStream_t s);
+
+// --- solve.hip ---------------------------------------------------------------
+size_t pcg_workspace_bytes(int64_t n);
+rpim_status solve_pcg(const int64_t* row_ptr, const int32_t* col_idx, const void* K, int precision, int64_t n,
+                      const double* f, double* x, double rtol, int64_t max_iter, void* ws, size_t ws_bytes,
+                      int64_t* iters, double* relres, hipStream_t s);
 
 // --- penalty.hip -------------------------------------------------------------
 size_t penalty_workspace_bytes(int64_t n_dof, int64_t n_fixed);

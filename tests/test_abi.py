@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     import paper_1802_04256_amd as rp
     lib = rp.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, -9):
         s = lib.rpim_status_string(code)
         assert s and s != b"unknown status"
 
@@ -51,6 +51,9 @@ def test_plan_create_rejects_bad_arguments():
     assert lib.rpim_penalty_workspace_bytes(0, 0) == 0
     assert lib.rpim_penalty_workspace_bytes(100, 10) >= 16 + 8 + 80
     assert lib.rpim_set_solver(None, 0, 0) == -1
+    assert lib.rpim_pcg_workspace_bytes(0) == 0 and lib.rpim_pcg_workspace_bytes(1000) >= 5 * 8 * 1000
+    assert lib.rpim_solve_pcg(None, None, None, 0, 10, None, None, ctypes.c_double(1e-8), 10, None, 0, None, None,
+                              None) == -1
     assert lib.rpim_factor_generation(None, None) == -1
     assert lib.rpim_autotune(None, None, None, ctypes.c_double(0.3), 0, None, None, None) == -1
 

@@ -252,3 +252,30 @@ def test_lds_kernel_equals_register_kernel(rp):
     plan.status()
     assert np.array_equal(d_reg, d_lds)
     assert np.array_equal(K_reg, K_lds)
+
+
+@pytest.mark.parametrize("name", ["slope_small", "jbox6", "cantilever"])
+def test_solver_kernels_agree(rp, name, oracle_mod):
+    # every moment-matrix kernel gives the same bits: gradients, K, and the kept factors the adjoint uses
+    # (the window kernel is compared with the oracle by the tests above)
+    import torch
+    prob = SMALL[name]()
+    print(f"[gpu case] solver kernels {name}: gps={prob.n_gp}", flush=True)
+    plan = rp.Plan.from_problem(prob)
+    plan.build_pattern()
+    E = torch.from_numpy(prob.cell_E).cuda()
+    out = {}
+    for kind in ("window", "panel", "lds"):
+        plan.set_solver(kind)
+        K = plan.assemble(cell_E=E, nu=prob.nu, keep_factors=True)
+        plan.status()
+        dK = torch.ones_like(K)
+        dE, dX = plan.assemble_backward(plan.node_xyz, E, prob.nu, dK)
+        out[kind] = (plan.dphi().cpu().numpy(), K.cpu().numpy(), dE.cpu().numpy(), dX.cpu().numpy())
+    for kind in ("panel", "lds"):
+        for a, b in zip(out["window"], out[kind]):
+            assert np.array_equal(a, b), kind
+    if name != "slope_small":
+        m = oracle_mod.OracleModel(prob)
+        m.build_pattern()
+        assert np.array_equal(out["panel"][1], m.assemble())

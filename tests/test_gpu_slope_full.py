@@ -102,3 +102,32 @@ def test_full_symmetry_and_rigid_modes(full):
     normK = sp.linalg.norm(S)
     res = np.linalg.norm(S @ U, axis=0) / (normK * np.linalg.norm(U, axis=0))
     assert res.max() < 1e-11
+
+
+def _chunk_hashes(K, row_ptr, n_nodes, chunk):
+    import hashlib
+    out = []
+    for a in range(0, n_nodes, chunk):
+        b = min(n_nodes, a + chunk)
+        out.append(hashlib.sha256(np.ascontiguousarray(K[row_ptr[3 * a]:row_ptr[3 * b]]).tobytes()).hexdigest())
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_K_equals_oracle_everywhere(full, precision):
+    # every entry of the full-size K, FP64 and mixed, bit for bit: SHA-256 of chunks of node rows against
+    # the values the oracle wrote (tests/golden/make_fixtures.py, CPU only)
+    import hashlib
+    import json
+    import os
+    prob, plan, m = full
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "slope_K_sha256.json")))
+    row_ptr = plan.row_ptr.cpu().numpy()
+    assert hashlib.sha256(row_ptr.tobytes()).hexdigest() == ref["row_ptr_sha256"]
+    assert hashlib.sha256(plan.col_idx.cpu().numpy().tobytes()).hexdigest() == ref["col_idx_sha256"]
+    K = plan.assemble(cell_E=prob.cell_E, nu=prob.nu, precision=precision).cpu().numpy()
+    plan.status()
+    got = _chunk_hashes(K, row_ptr, prob.n_nodes, ref["chunk_node_rows"])
+    bad = [i for i, (a, b) in enumerate(zip(got, ref[precision]["chunks"])) if a != b]
+    assert not bad, f"node-row chunks differing from the oracle: {bad}"
+    assert hashlib.sha256(K.tobytes()).hexdigest() == ref[precision]["sha256"]
