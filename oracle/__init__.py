@@ -50,6 +50,8 @@ def lib():
         L.orcl_penalty.argtypes = [i64p, i32p, vp, C.c_int, i64, i32p, dp, i64, d, dp, dp]
         L.orcl_assemble_backward.argtypes = [vp, dp, dp, d, dp, i64p, i64, dp, dp]
         L.orcl_dot_q.argtypes = [vp, dp, dp, d, dp, i64p, i64, dp]
+        L.orcl_body_force.argtypes = [vp, dp, dp, dp]
+        L.orcl_gauss_stress.argtypes = [vp, dp, dp, d, dp, dp]
         L.orcl_pow_cr.restype = d
         L.orcl_pow_cr.argtypes = [d, d]
         L.orcl_pow_fallbacks.restype = C.c_long
@@ -156,6 +158,24 @@ class OracleModel:
                                             _p(Kb), _p(g), 0 if g is None else len(g), _p(dE), _p(dX)),
                "assemble_backward")
         return dE, dX
+
+    def body_force(self, gp_force, node_xyz=None):
+        """f_I = sum_g w_g phi_I(x_g) b_g for b_g = gp_force[g] (force per unit volume), shape [N, 3]."""
+        X = None if node_xyz is None else np.ascontiguousarray(node_xyz, np.float64)
+        b = np.ascontiguousarray(np.broadcast_to(gp_force, (self.prob.n_gp, 3)), np.float64)
+        f = np.empty((self.prob.n_nodes, 3))
+        _check(lib().orcl_body_force(self.h, _p(X), _p(b), _p(f)), "body_force")
+        return f
+
+    def gauss_stress(self, u, cell_E=None, nu=None, node_xyz=None):
+        """Stress [xx, yy, zz, yz, xz, xy] at every Gauss point for nodal displacements u [N, 3]."""
+        E = np.ascontiguousarray(self.prob.cell_E if cell_E is None else cell_E, np.float64)
+        X = None if node_xyz is None else np.ascontiguousarray(node_xyz, np.float64)
+        uu = np.ascontiguousarray(u, np.float64).reshape(-1)
+        sig = np.empty((self.prob.n_gp, 6))
+        _check(lib().orcl_gauss_stress(self.h, _p(X), _p(E), self.prob.nu if nu is None else nu, _p(uu), _p(sig)),
+               "gauss_stress")
+        return sig
 
     def dot_q(self, Kbar, gps, node_xyz=None, cell_E=None, nu=None):
         """<Kbar, sum_{g in gps} k^g> in __float128 (frozen supports) -> (hi, lo)."""

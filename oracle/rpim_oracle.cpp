@@ -457,6 +457,74 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
   return OK;
 }
 
+// After the solve (GeoMFree3D Sec. 2: the displacements are found first, the
+// stresses from them).  Body force: f_I = sum_g w_g phi_I(x_g) b_g, b_g the
+// force per unit volume at Gauss point g, summed per node in ascending g:
+// e = fl(w_g * phi_a) * b_k, f = f + e.  phi comes from the value right-hand
+// side [R(x_g); 1, 0, 0, 0] of the same solve (gp_solve with four columns).
+int orcl_body_force(void* h, const double* node_xyz, const double* gp_force, double* f) {
+  Model& m = *(Model*)h;
+  if (!m.built) return E_STATE;
+  const double* X = node_xyz ? node_xyz : m.node.data();
+  std::fill(f, f + 3 * m.N, 0.0);
+  std::vector<double> sol;
+  for (int64_t g = 0; g < m.G; ++g) {
+    int st = gp_solve<double>(m, X, g, 4, sol);
+    if (st != OK) return st;
+    const int64_t b0 = m.gp_ptr[g];
+    const int n = (int)(m.gp_ptr[g + 1] - b0), Nn = n + 4;
+    for (int a = 0; a < n; ++a) {
+      const double c = m.wdet[g] * sol[(size_t)3 * Nn + a];
+      for (int k = 0; k < 3; ++k) {
+        const int64_t d = 3 * (int64_t)m.gp_nbr[b0 + a] + k;
+        f[d] = f[d] + c * gp_force[3 * g + k];
+      }
+    }
+  }
+  return OK;
+}
+
+// Stress at every Gauss point from nodal displacements u (dof 3*node + comp):
+// H_ij = sum_a u_{S[a], i} dphi_a/dx_j as fma(u, dphi, H) in ascending a from
+// +0; eps_ij = 0.5 * (H_ij + H_ji); tr = (eps_00 + eps_11) + eps_22;
+// with lc = fl(E_c * lam_hat), mc = fl(E_c * mu_hat):
+// sigma_ii = fma(lc, tr, fl(2 mc) * eps_ii), sigma_ij = fl(2 mc) * eps_ij;
+// stored as [xx, yy, zz, yz, xz, xy] per point.
+int orcl_gauss_stress(void* h, const double* node_xyz, const double* cell_E, double nu, const double* u,
+                      double* sigma) {
+  Model& m = *(Model*)h;
+  if (!m.built) return E_STATE;
+  if (!(nu > -1.0 && nu < 0.5)) return E_ARG;
+  const double* X = node_xyz ? node_xyz : m.node.data();
+  double lam, mu;
+  lame_hat(nu, &lam, &mu);
+  std::vector<double> sol;
+  for (int64_t g = 0; g < m.G; ++g) {
+    int st = gp_solve<double>(m, X, g, 3, sol);
+    if (st != OK) return st;
+    const int64_t b0 = m.gp_ptr[g];
+    const int n = (int)(m.gp_ptr[g + 1] - b0), Nn = n + 4;
+    double H[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int a = 0; a < n; ++a) {
+      const int64_t I = m.gp_nbr[b0 + a];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[i][j] = std::fma(u[3 * I + i], sol[(size_t)j * Nn + a], H[i][j]);
+    }
+    double e[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) e[i][j] = 0.5 * (H[i][j] + H[j][i]);
+    const double tr = (e[0][0] + e[1][1]) + e[2][2];
+    const double c = cell_E[m.cell[g]];
+    const double lc = c * lam, mc2 = 2.0 * (c * mu);
+    double* s = sigma + 6 * g;
+    for (int i = 0; i < 3; ++i) s[i] = std::fma(lc, tr, mc2 * e[i][i]);
+    s[3] = mc2 * e[1][2];
+    s[4] = mc2 * e[0][2];
+    s[5] = mc2 * e[0][1];
+  }
+  return OK;
+}
+
 // Stage 2: penalty BCs.  alpha = factor * max_i K_ii over all dofs (before the
 // update); K_dd += alpha and rhs_d += alpha * u_bar_d for each fixed dof d.
 int orcl_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, int precision,
