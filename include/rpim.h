@@ -179,6 +179,26 @@ rpim_status rpim_apply_penalty_bc(const int64_t* row_ptr, const int32_t* col_idx
                                   double* alpha, int32_t* status, void* workspace, size_t workspace_bytes,
                                   void* stream);
 
+/* After the solve (GeoMFree3D Sec. 2: displacements first, then the stresses;
+ * Sec. 3, Example 1: a cube loaded by its own weight).  Asynchronous.
+ *
+ * rpim_shape_values: phi double[sum_n], entry gp_ptr[g] + a = phi_a(x_g) for
+ *   support node a of point g, the first n entries of G_g^-1 [R(x_g); 1, 0, 0, 0]
+ *   (the value right-hand side of the moment system), from the LU factors
+ *   kept by the last rpim_assemble with keep_factors = 1 (RPIM_E_STATE
+ *   otherwise); node_xyz must be the coordinates of that call.
+ * rpim_body_force: f double[3N] = sum_g w_g phi_I(x_g) b_g per node I and
+ *   component, b_g = gp_force[3g .. 3g+2] the force per unit volume at point g
+ *   (device), summed in ascending g; phi from rpim_shape_values.
+ * rpim_gauss_stress: sigma double[G][6] = E_c D(nu) eps(u) at every Gauss point
+ *   in the order [xx, yy, zz, yz, xz, xy], eps the symmetric gradient of the
+ *   nodal displacements u double[3N] through the shape-function gradients of
+ *   the last rpim_assemble (RPIM_E_STATE before any). */
+rpim_status rpim_shape_values(rpim_plan* plan, const double* node_xyz, double* phi, void* stream);
+rpim_status rpim_body_force(rpim_plan* plan, const double* phi, const double* gp_force, double* f, void* stream);
+rpim_status rpim_gauss_stress(rpim_plan* plan, const double* cell_E, double nu, const double* u, double* sigma,
+                              void* stream);
+
 /* Stage 3: solve K x = rhs (GeoMFree3D Sec. 2, stage 3: the assembled sparse
  * system is solved on the GPU) by conjugate gradients with the Jacobi
  * (diagonal) preconditioner; K symmetric positive definite, e.g. an assembled

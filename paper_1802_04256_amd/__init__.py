@@ -94,6 +94,9 @@ def lib():
         L.rpim_autotune.argtypes = [vp, vp, vp, d, i32, vp, vp, C.POINTER(_Tuning)]
         L.rpim_set_gather_waves.argtypes = [vp, i32, i32]
         L.rpim_set_solver.argtypes = [vp, i32, i32]
+        L.rpim_shape_values.argtypes = [vp, vp, vp, vp]
+        L.rpim_body_force.argtypes = [vp, vp, vp, vp, vp]
+        L.rpim_gauss_stress.argtypes = [vp, vp, d, vp, vp, vp]
         L.rpim_tuning_cache_save.argtypes = [C.c_char_p]
         L.rpim_tuning_cache_load.argtypes = [C.c_char_p]
         L.rpim_tuning_cache_clear.restype = None
@@ -106,7 +109,8 @@ def lib():
                   "rpim_get_dphi", "rpim_pow_cr", "rpim_rebuild_pattern", "rpim_profile_enable",
                   "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves", "rpim_set_solver",
                   "rpim_factor_generation", "rpim_apply_penalty_bc_noalloc",
-                  "rpim_solve_pcg", "rpim_tuning_cache_save", "rpim_tuning_cache_load"):
+                  "rpim_solve_pcg", "rpim_tuning_cache_save", "rpim_tuning_cache_load",
+                  "rpim_shape_values", "rpim_body_force", "rpim_gauss_stress"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -300,6 +304,34 @@ class Plan:
         _check(lib().rpim_assemble_backward(self._h, _ptr(X), _ptr(E), float(nu), _ptr(dK), _ptr(dE), _ptr(dX),
                                             _stream()), "rpim_assemble_backward")
         return dE, dX
+
+    def shape_values(self, node_xyz=None):
+        """phi_a(x_g) for every support entry [sum_n], from the factors kept by the last
+        assemble(keep_factors=True) at these coordinates."""
+        torch = _torch()
+        X = self.node_xyz if node_xyz is None else _dev(node_xyz, torch.float64, self.device)
+        phi = torch.empty(self.info()["sum_n"], dtype=torch.float64, device=self.device)
+        _check(lib().rpim_shape_values(self._h, _ptr(X), _ptr(phi), _stream()), "rpim_shape_values")
+        return phi
+
+    def body_force(self, phi, gp_force):
+        """Nodal body force [N, 3] from force per unit volume at each Gauss point ([3] or [G, 3])."""
+        torch = _torch()
+        b = _dev(gp_force, torch.float64, self.device)
+        b = b.expand(self.n_gp, 3).contiguous() if b.dim() == 1 else b.contiguous()
+        f = torch.empty(self.n_nodes, 3, dtype=torch.float64, device=self.device)
+        _check(lib().rpim_body_force(self._h, _ptr(phi), _ptr(b), _ptr(f), _stream()), "rpim_body_force")
+        return f
+
+    def gauss_stress(self, u, cell_E, nu=0.3):
+        """Stress [G, 6] (xx, yy, zz, yz, xz, xy) from nodal displacements u ([N, 3] or [3N])."""
+        torch = _torch()
+        uu = _dev(u, torch.float64, self.device).reshape(-1).contiguous()
+        E = _dev(cell_E, torch.float64, self.device)
+        sig = torch.empty(self.n_gp, 6, dtype=torch.float64, device=self.device)
+        _check(lib().rpim_gauss_stress(self._h, _ptr(E), float(nu), _ptr(uu), _ptr(sig), _stream()),
+               "rpim_gauss_stress")
+        return sig
 
     def status(self, raise_on_error=True):
         bad = C.c_int64()

@@ -537,6 +537,26 @@ rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t*
                                 alpha, status, (hipStream_t)stream);
 }
 
+rpim_status rpim_shape_values(rpim_plan* p, const double* node_xyz, double* phi, void* stream) {
+  if (!p || !node_xyz || !phi) return RPIM_E_ARG;
+  if (!p->built || !p->have_factors) return RPIM_E_STATE;
+  return launch_shape_values(p, node_xyz, phi, (hipStream_t)stream);
+}
+
+rpim_status rpim_body_force(rpim_plan* p, const double* phi, const double* gp_force, double* f, void* stream) {
+  if (!p || !phi || !gp_force || !f) return RPIM_E_ARG;
+  if (!p->built) return RPIM_E_STATE;
+  return launch_body_force(p, phi, gp_force, f, (hipStream_t)stream);
+}
+
+rpim_status rpim_gauss_stress(rpim_plan* p, const double* cell_E, double nu, const double* u, double* sigma,
+                              void* stream) {
+  if (!p || !cell_E || !u || !sigma) return RPIM_E_ARG;
+  if (!p->built || !p->dphi) return RPIM_E_STATE;
+  if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
+  return launch_gauss_stress(p, cell_E, nu, u, sigma, (hipStream_t)stream);
+}
+
 size_t rpim_pcg_workspace_bytes(int64_t n_dof) {
   if (n_dof <= 0) return 0;
   return pcg_workspace_bytes(n_dof);

@@ -20,6 +20,7 @@
 #include <cfloat>
 
 #include "dd_pow.h"
+#include "kept_solve.h"
 #include "rpim_internal.h"
 
 namespace rpim {
@@ -177,7 +178,6 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   // packed factors, column-major F[c*N + p]: u_pc for p <= c; for p > c the
   // multiplier of step c for the row at position p after that step's interchange
   const double* Fm = lu + lu_off[g];
-  const double* U = Fm;
   for (int idx = tid; idx < 3 * N; idx += nT) gm[idx] = gam[3 * o + idx];
   for (int i = tid; i < n; i += nT) {
     const int32_t sidx = gp_nbr[b0 + i];
@@ -195,89 +195,8 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   if (own && tid < n)
     for (int k = 0; k < 3; ++k) b[k] = pbar[3 * (b0 + tid) + k];
   __syncthreads();
-  // Forward substitution on original rows, replaying the interchanges: thread r
-  // tracks the position of its row (the pivot of step k takes position k, the
-  // row that held k takes the pivot's old position).  Factor entries are read
-  // PF steps ahead; a second tracker replays the interchanges PF steps ahead of
-  // the first, so each entry is read at the position the row will hold then.
-  constexpr int PF = 8;
-  const auto interchange = [&](int k, int q) {  // position after step k of a row at q before it
-    const int pk = ppos[k];
-    return q == pk ? k : (q == k ? pk : q);
-  };
-  int pos = own ? tid : N;   // position before the current step
-  int posa = pos;            // position after the steps already prefetched
-  double fcur[PF], fnxt[PF];
-  const auto fetch = [&](int k, int q) { return Fm[(int64_t)k * N + (q < N ? q : N - 1)]; };
-#pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    if (j < N) {
-      posa = interchange(j, posa);
-      fcur[j] = fetch(j, posa);
-    }
-  }
-  for (int k0 = 0; k0 < N; k0 += PF) {
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      const int kk = k0 + PF + j;
-      if (kk < N) {  // uniform
-        posa = interchange(kk, posa);
-        fnxt[j] = fetch(kk, posa);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      const int k = k0 + j;
-      if (k < N) {  // uniform
-        const int after = interchange(k, pos);
-        if (own && after == k) {  // my row is the pivot of step k
-          for (int c = 0; c < 3; ++c) y[c * N + k] = b[c];
-        }
-        pos = after;
-        __syncthreads();
-        if (own && pos > k)
-          for (int c = 0; c < 3; ++c) b[c] = __builtin_fma(-fcur[j], y[c * N + k], b[c]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < PF; ++j) fcur[j] = fnxt[j];
-  }
-  __syncthreads();
-  // back substitution by position: thread p holds y_p; u_{p,k} read PF steps ahead
-  const int trow = own ? tid : 0;
-  double yp[3] = {0.0, 0.0, 0.0};
-  if (own)
-    for (int j = 0; j < 3; ++j) yp[j] = y[j * N + tid];
-#pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    const int kk = N - 1 - j;
-    fcur[j] = U[(int64_t)(kk >= 0 ? kk : 0) * N + trow];
-  }
-  for (int k0 = N - 1; k0 >= 0; k0 -= PF) {
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      const int kk = k0 - PF - j;
-      fnxt[j] = U[(int64_t)(kk >= 0 ? kk : 0) * N + trow];
-    }
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
-      const int k = k0 - j;
-      if (k >= 0) {  // uniform
-        const double uk = fcur[j];  // u_{tid,k}
-        if (tid == k)
-          for (int c = 0; c < 3; ++c) {
-            yp[c] = yp[c] / uk;
-            lamv[c * N + k] = yp[c];
-          }
-        __syncthreads();
-        if (tid < k)
-          for (int c = 0; c < 3; ++c) yp[c] = __builtin_fma(-uk, lamv[c * N + k], yp[c]);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < PF; ++j) fcur[j] = fnxt[j];
-  }
-  __syncthreads();
+  // lambda_k = G^-1 [Phibar_k; 0] with the kept factors (G symmetric)
+  kept_solve<3>(Fm, ppos, N, tid, b, y, lamv);
   // chain rule: four threads per support node a, partial sums over b = sub mod 4
   // in ascending b.  R_ab is read as entry (S[b], S[a]) of row S[b] of the pair
   // table (symmetric bit for bit), four b at a time with the loads first: one

@@ -195,6 +195,12 @@ rpim_status launch_pow_test(const double* x, double q, double* y, int64_t n, hip
 rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, double nu,
                             const double* dK, double* dE, double* dX, hipStream_t s);
 
+// --- post.hip ----------------------------------------------------------------
+rpim_status launch_shape_values(rpim_plan* p, const double* X, double* phi, hipStream_t s);
+rpim_status launch_body_force(rpim_plan* p, const double* phi, const double* gp_force, double* f, hipStream_t s);
+rpim_status launch_gauss_stress(rpim_plan* p, const double* E, double nu, const double* u, double* sigma,
+                                hipStream_t s);
+
 // --- solve.hip ---------------------------------------------------------------
 size_t pcg_workspace_bytes(int64_t n);
 rpim_status solve_pcg(const int64_t* row_ptr, const int32_t* col_idx, const void* K, int precision, int64_t n,
