@@ -34,7 +34,8 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # counter runs of this script, each scaled by what the same counter reads for a plain 1 GiB device copy
 # (fetch x2.000, write x1.000).  The summary and its commands are in profiles/.  The figure belongs to
 # the kernel sources it was measured on: any change to them reports traffic as null until re-measured.
-SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/assemble.hip",
+SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/shape_panel.hip",
+                 "paper_1802_04256_amd/csrc/shape_common.h", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
 SHAPE_TRAFFIC = {"sources_sha256": "3cdd9b187e9f4577b3e909845dd5c40721d78f462ff639176c2fc55c40b49cd8", "bytes_per_step": 3.903e10}
 
@@ -310,12 +311,13 @@ def main():
 
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
+        # one streaming kernel that reads and writes nbytes each (negation: a kernel name of its own)
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        log(f"copy calibration: fill {nbytes} B, copy {nbytes} B -> {nbytes} B")
+        log(f"copy calibration: neg kernel reads {nbytes} B, writes {nbytes} B")
 
     def step():
         plan.rebuild_pattern(X)

@@ -373,9 +373,12 @@ __device__ __forceinline__ void back_substitute_and_store(const double* lds, int
     if (dphi32) dphi32[3 * (b0 + aa) + j] = (float)xsol[j][aa];
   }
   if (keep) {
-    // U by position into the packed factor matrix: F[c*N + p] = u_pc, c >= p
+    // U by position into the packed factor matrix: F[c*N + p] = u_pc, c >= p;
+    // row c of F in one store per wave (lane p writes column p)
     if (t < N) {
-      for (int c = t; c < N; ++c) F[(int64_t)c * N + t] = lds[my_off + (c - t)];
+#pragma unroll 4
+      for (int c = t & ~63; c < N; ++c)
+        if (t <= c) F[(int64_t)c * N + t] = lds[my_off + (c - t)];
     }
     const int64_t o = b0 + 4 * g;
     for (int i = t; i < N; i += T) piv_out[o + i] = pivpos[i];

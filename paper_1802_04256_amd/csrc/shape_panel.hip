@@ -53,7 +53,7 @@ __host__ __device__ constexpr int uoff(int k) {
 }
 
 template <int NMAX, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_shape_panel(
+__global__ void __launch_bounds__(64 * WAVES, NMAX <= 88 ? 2 : 1) k_shape_panel(
     const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr, const int32_t* gp_nbr,
     const int64_t* blk_ptr, const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm, const double* R,
     const double* X, const double* gp_xyz, double C2, double q, double* dphi, float* dphi32, int keep,
@@ -78,6 +78,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_panel(
   __shared__ int pivpos[NMAX];  // position the pivot of each step held before it
   __shared__ double xg[3];
   __shared__ double rmax[WAVES];
+  __shared__ int mpos[64];  // hand-over: positions of the rows that move
+  __shared__ int mcount, hstate;
   const BuildLds bl = build_lds<NMAX>(lds);
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -92,147 +94,230 @@ __global__ void __launch_bounds__(64 * WAVES) k_shape_panel(
   if (hard) flag_error(st, kFlagPow, g);
   const double tiny = singular_threshold<NMAX, WAVES, WC>(a, N, lane, w, rmax);
 
-  int pos = t;              // current position of my row
-  const bool real = t < N;  // padding rows never take part
+  int pos = t;        // current position of my row
+  bool real = t < N;  // padding rows never take part (a row handed over is real in its new lane)
   double* F = keep ? lu + lu_off[g] : nullptr;  // packed factors (multipliers by position)
-#pragma unroll 1
-  for (int k0 = 0;; k0 += NB) {
-    const int len = NMAX + 3 - k0;            // window elements in use (columns k0..NMAX-1, 3 rhs)
-    const int nbe = N - k0 < NB ? N - k0 : NB;  // pivot steps in this panel
-    // ---- 1. pivot steps inside the panel ---------------------------------------------
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      if (i < nbe) {  // uniform
-        const int k = k0 + i;
-        const bool active = real && pos >= k;
-        double v;
-        unsigned key;
-        wave_argmax(fabs(a[i]), active, ((unsigned)pos << 8) | (unsigned)t, &v, &key);
-        double best = v;
-        unsigned bkey = key;
-        double u[NB];  // pivot row, window elements i..NB-1 (panel columns k..k0+NB-1)
-        if constexpr (WAVES > 1) {
-          const int buf = i & 1;
-          if (lane == 0) {
-            Cand c;
-            c.v = key == 0xFFFFFFFFu ? -1.0 : v;
-            c.key = key;
-            c.pad = 0;
-            cand[buf][w] = c;
-          }
-          if (key != 0xFFFFFFFFu && t == (int)(key & 255u)) {
-#pragma unroll
-            for (int j = 0; j < NB - i; ++j) prow[buf][w][j] = a[i + j];
-          }
-          __syncthreads();
-          int wb = 0;
-          best = cand[buf][0].v;
-          bkey = cand[buf][0].key;
-#pragma unroll
-          for (int x = 1; x < WAVES; ++x) {
-            const Cand c = cand[buf][x];
-            const bool take = c.v > best || (c.v == best && c.key < bkey);
-            best = take ? c.v : best;
-            bkey = take ? c.key : bkey;
-            wb = take ? x : wb;
-          }
-#pragma unroll
-          for (int j = 0; j < NB - i; ++j) u[j] = prow[buf][wb][j];
-        } else {
-          if (key == 0xFFFFFFFFu) best = -1.0;
-          const int L = (int)(key & 63u);
-#pragma unroll
-          for (int j = 0; j < NB - i; ++j) u[j] = readlane_f64(a[i + j], L);
-        }
-        if (!(best > tiny)) {
-          if (t == 0) flag_error(st, kFlagSingular, g);
-          return;  // uniform: every thread saw the same best
-        }
-        const int prow_id = (int)(bkey & 255u), ppos = (int)(bkey >> 8);
-        if (t == 0) pivpos[k] = ppos;
-        if (t == prow_id) pos = k;
-        else if (pos == k) pos = ppos;
-        if (real && pos > k) {  // eliminated at this step
-          const double l = a[i] / u[0];
-          a[i] = l;  // kept in place of the panel column for steps 3 and 4
-#pragma unroll
-          for (int j = 1; j < NB - i; ++j) a[i + j] = __builtin_fma(-l, u[j], a[i + j]);
-          if (keep) F[(int64_t)k * N + pos] = l;
-        }
+  // One panel from column k0 on, by every wave of the workgroup or (ONE) by
+  // wave 0 alone once it holds every row still active.  Returns 1 when every
+  // row is pivoted, 2 on a singular pivot (flagged), 0 otherwise.
+  auto panel = [&](auto one_tag, const int k0) -> int {
+    constexpr bool ONE = decltype(one_tag)::value || WAVES == 1;
+    constexpr int TT = ONE ? 64 : T;  // threads at work
+    const auto sync = [&] {
+      if constexpr (ONE && WAVES > 1) {  // wave 0 alone: its LDS accesses complete in program order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      } else {
+        __syncthreads();
       }
-    }
-    // ---- 2. the panel's pivot rows publish their windows ------------------------------
-    {
-      const int pp = pos - k0;  // position inside the panel
-      if (real && pp >= 0 && pp < nbe) {
-#pragma unroll
-        for (int j = 0; j < NB; j += 2)
-          *reinterpret_cast<double2*>(&p11[pp][j]) = make_double2(a[j], a[j + 1]);
-        double* dst = lds + uoff<NMAX>(k0 + pp) - pp;  // element j of the window -> dst[j]
-#pragma unroll
-        for (int j = NB; j < WC; ++j)
-          if (j < len) dst[j] = a[j];
-      }
-    }
-    __syncthreads();
-    // ---- 3. trailing parts of the panel's U rows, one thread per column ---------------
-    // The earlier rows' finished elements are read back from LDS rather than
-    // kept in registers (the window stays live here), one row at a time.
-    for (int j = NB + t; j < len; j += T) {
+    };
+      const int len = NMAX + 3 - k0;            // window elements in use (columns k0..NMAX-1, 3 rhs)
+      const int nbe = N - k0 < NB ? N - k0 : NB;  // pivot steps in this panel
+      // ---- 1. pivot steps inside the panel ---------------------------------------------
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         if (i < nbe) {  // uniform
-          double* e = lds + uoff<NMAX>(k0 + i) + (j - i);
-          double v = *e;
+          const int k = k0 + i;
+          const bool active = real && pos >= k;
+          double v;
+          unsigned key;
+          wave_argmax(fabs(a[i]), active, ((unsigned)pos << 8) | (unsigned)t, &v, &key);
+          double best = v;
+          unsigned bkey = key;
+          double u[NB];  // pivot row, window elements i..NB-1 (panel columns k..k0+NB-1)
+          if constexpr (WAVES > 1) {  // candidates and the pivot row through LDS
+            const int buf = i & 1;
+            if (lane == 0) {
+              Cand c;
+              c.v = key == 0xFFFFFFFFu ? -1.0 : v;
+              c.key = key;
+              c.pad = 0;
+              cand[buf][w] = c;
+            }
+            if (key != 0xFFFFFFFFu && t == (int)(key & 255u)) {
 #pragma unroll
-          for (int i2 = 0; i2 < i; ++i2) {
-            v = __builtin_fma(-p11[i][i2], lds[uoff<NMAX>(k0 + i2) + (j - i2)], v);
-            if ((i2 & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four terms' loads in flight at most
+              for (int j = 0; j < NB - i; ++j) prow[buf][w][j] = a[i + j];
+            }
+            sync();
+            int wb = 0;
+            best = cand[buf][0].v;
+            bkey = cand[buf][0].key;
+#pragma unroll
+            for (int x = 1; x < (ONE ? 1 : WAVES); ++x) {
+              const Cand c = cand[buf][x];
+              const bool take = c.v > best || (c.v == best && c.key < bkey);
+              best = take ? c.v : best;
+              bkey = take ? c.key : bkey;
+              wb = take ? x : wb;
+            }
+#pragma unroll
+            for (int j = 0; j < NB - i; ++j) u[j] = prow[buf][wb][j];
+          } else {
+            if (key == 0xFFFFFFFFu) best = -1.0;
+            const int L = (int)(key & 63u);
+#pragma unroll
+            for (int j = 0; j < NB - i; ++j) u[j] = readlane_f64(a[i + j], L);
           }
-          *e = v;
-          __builtin_amdgcn_sched_barrier(0);
+          if (!(best > tiny)) {
+            if (t == 0) flag_error(st, kFlagSingular, g);
+            return 2;  // uniform: every working thread saw the same best
+          }
+          const int prow_id = (int)(bkey & 255u), ppos = (int)(bkey >> 8);
+          if (t == 0) pivpos[k] = ppos;
+          if (t == prow_id) pos = k;
+          else if (pos == k) pos = ppos;
+          if (real && pos > k) {  // eliminated at this step
+            const double l = a[i] / u[0];
+            a[i] = l;  // kept in place of the panel column for steps 3 and 4
+#pragma unroll
+            for (int j = 1; j < NB - i; ++j) a[i + j] = __builtin_fma(-l, u[j], a[i + j]);
+            if (keep) F[(int64_t)k * N + pos] = l;
+          }
         }
       }
-    }
-    // U rows' panel part: row k0+i from its diagonal (in the last panel the
-    // right-hand sides may sit inside the panel's sixteen window elements)
-    for (int idx = t; idx < NB * NB; idx += T) {
-      const int i = idx / NB, e = idx - i * NB;
-      if (i < nbe && e >= i && e < len) lds[uoff<NMAX>(k0 + i) + (e - i)] = p11[i][e];
-    }
-    __syncthreads();
-    if (k0 + NB >= N) break;  // uniform: every row is pivoted
-    // ---- 4. trailing update and shift for the rows still active -----------------------
-    // Each half block of the window (eight elements from 8 h) takes the
-    // sixteen updates in ascending step order; the U values of step i + 1 are
-    // loaded while step i's multiply-adds run (two sets of eight in flight).
-    if (real && pos >= k0 + NB) {
+      // ---- 2. the panel's pivot rows publish their windows ------------------------------
+      {
+        const int pp = pos - k0;  // position inside the panel
+        if (real && pp >= 0 && pp < nbe) {
 #pragma unroll
-      for (int h = 2; h < 2 * NBLK; ++h) {
-        if (8 * h < len) {  // uniform
-          double ub[2][8];
-          auto load = [&](int i, double(&dst)[8]) {
-            const double* urow = lds + uoff<NMAX>(k0 + i) + (8 * h - i);  // U_{k0+i} at window column 8 h
+          for (int j = 0; j < NB; j += 2)
+            *reinterpret_cast<double2*>(&p11[pp][j]) = make_double2(a[j], a[j + 1]);
+          double* dst = lds + uoff<NMAX>(k0 + pp) - pp;  // element j of the window -> dst[j]
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (8 * h + e < WC) dst[e] = urow[e];
-          };
-          load(0, ub[0]);
+          for (int j = NB; j < WC; ++j)
+            if (j < len) dst[j] = a[j];
+        }
+      }
+      sync();
+      // ---- 3. trailing parts of the panel's U rows, one thread per column ---------------
+      // The earlier rows' finished elements are read back from LDS rather than
+      // kept in registers (the window stays live here), one row at a time.
+      for (int j = NB + t; j < len; j += TT) {
 #pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            if (i + 1 < NB) load(i + 1, ub[(i + 1) & 1]);
-            const double nl = -a[i];
+        for (int i = 0; i < NB; ++i) {
+          if (i < nbe) {  // uniform
+            double* e = lds + uoff<NMAX>(k0 + i) + (j - i);
+            double v = *e;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (8 * h + e < WC) a[8 * h + e] = __builtin_fma(nl, ub[i & 1][e], a[8 * h + e]);
+            for (int i2 = 0; i2 < i; ++i2) {
+              v = __builtin_fma(-p11[i][i2], lds[uoff<NMAX>(k0 + i2) + (j - i2)], v);
+              if ((i2 & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four terms' loads in flight at most
+            }
+            *e = v;
             __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
+      // U rows' panel part: row k0+i from its diagonal (in the last panel the
+      // right-hand sides may sit inside the panel's sixteen window elements)
+      for (int idx = t; idx < NB * NB; idx += TT) {
+        const int i = idx / NB, e = idx - i * NB;
+        if (i < nbe && e >= i && e < len) lds[uoff<NMAX>(k0 + i) + (e - i)] = p11[i][e];
+      }
+      sync();
+      if (k0 + NB >= N) return 1;  // uniform: every row is pivoted
+      // ---- 4. trailing update and shift for the rows still active -----------------------
+      // Each half block of the window (eight elements from 8 h) takes the
+      // sixteen updates in ascending step order; the U values of step i + 1 are
+      // loaded while step i's multiply-adds run (two sets of eight in flight).
+      if (real && pos >= k0 + NB) {
 #pragma unroll
-      for (int j = 0; j + NB < WC; ++j) a[j] = a[j + NB];
+        for (int h = 2; h < 2 * NBLK; ++h) {
+          if (8 * h < len) {  // uniform
+            double ub[2][8];
+            auto load = [&](int i, double(&dst)[8]) {
+              const double* urow = lds + uoff<NMAX>(k0 + i) + (8 * h - i);  // U_{k0+i} at window column 8 h
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                if (8 * h + e < WC) dst[e] = urow[e];
+            };
+            load(0, ub[0]);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+              if (i + 1 < NB) load(i + 1, ub[(i + 1) & 1]);
+              const double nl = -a[i];
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                if (8 * h + e < WC) a[8 * h + e] = __builtin_fma(nl, ub[i & 1][e], a[8 * h + e]);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j + NB < WC; ++j) a[j] = a[j + NB];
+      }
+      return 0;
+  };
+
+  int state = 0;
+  int k0 = 0;
+  // the hand-over's extra registers would cost the largest window its spill-free fit
+  constexpr bool kHandOver = WAVES > 1 && NMAX <= 88;
+  if constexpr (!kHandOver) {
+#pragma unroll 1
+    for (;; k0 += NB)
+      if ((state = panel(std::false_type{}, k0)) != 0) break;
+  } else {
+#pragma unroll 1
+    for (;; k0 += NB) {
+      state = panel(std::false_type{}, k0);
+      if (state != 0 || N - (k0 + NB) <= 64) break;  // uniform
+    }
+    if (state == 0) {
+      // ---- hand-over: the rows still active fit in one wave -------------------------
+      // Wave 1's active rows move, sixteen window elements at a time through
+      // the U storage of rows not yet reached, to lanes of wave 0 whose rows
+      // are pivoted; wave 0 then runs the remaining panels alone (no barrier
+      // per pivot step) and wave 1 waits for the back substitution.  A row's
+      // lane carries no meaning past the build: factors are stored by position.
+      k0 += NB;
+      constexpr int KH = 16 * ((NMAX - 64 + 15) / 16);  // latest hand-over column
+      static_assert(uoff<NMAX>(NMAX) + 16 - uoff<NMAX>(KH) >= 64 * 16, "hand-over buffer fits");
+      double* hb = lds + uoff<NMAX>(k0);
+      const int lenn = NMAX + 3 - k0;  // window elements in use from column k0 on
+      const bool act = real && pos >= k0;
+      const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+      const unsigned long long mask = __ballot(w == 1 ? act : !act);  // wave 1: movers; wave 0: free lanes
+      const int r = __popcll(mask & below);
+      if (w == 1) {
+        if (act) mpos[r] = pos;
+        if (lane == 0) mcount = __popcll(mask);
+      }
+      __syncthreads();
+      const bool take = w == 0 && !act && r < mcount;
+#pragma unroll
+      for (int c = 0; c < NBLK; ++c) {
+        if (16 * c < lenn) {  // uniform
+          if (w == 1 && act) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+              if (16 * c + e < WC) hb[16 * r + e] = a[16 * c + e];
+          }
+          __syncthreads();
+          if (take) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+              if (16 * c + e < WC) a[16 * c + e] = hb[16 * r + e];
+          }
+          __syncthreads();
+        }
+      }
+      if (take) {
+        pos = mpos[r];
+        real = true;
+      }
+      if (w == 0) {
+#pragma unroll 1
+        for (;; k0 += NB)
+          if ((state = panel(std::true_type{}, k0)) != 0) break;
+        if (t == 0) hstate = state;
+      }
+      __syncthreads();  // wave 1 waits here for wave 0's factorization
+      state = hstate;
     }
   }
+  if (state == 2) return;  // singular (uniform)
 
   // ---- back substitution by position from the U rows, then the outputs ----------
   back_substitute_and_store<NMAX, WAVES>(lds, t < N ? uoff<NMAX>(t) : 0, xsol, pivpos, t, N, n, g, b0, dphi, dphi32,
