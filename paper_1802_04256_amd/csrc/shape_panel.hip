@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(64 * WAVES, NMAX <= 88 ? 2 : 1) k_shape_panel(
           double best = v;
           unsigned bkey = key;
           double u[NB];  // pivot row, window elements i..NB-1 (panel columns k..k0+NB-1)
-          if constexpr (WAVES > 1) {  // candidates and the pivot row through LDS
+          if constexpr (WAVES > 1 && !ONE) {  // candidates and the pivot row through LDS
             const int buf = i & 1;
             if (lane == 0) {
               Cand c;
