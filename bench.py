@@ -31,13 +31,13 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (and matrix) peak
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
 # HBM bytes moved by all moment-matrix kernel launches (k_shape*) of one step: FETCH_SIZE and WRITE_SIZE
-# counter runs of this script, each scaled by what the same counter reads for a plain 1 GiB device copy
-# (fetch x2.000, write x1.000).  The summary and its commands are in profiles/.  The figure belongs to
+# counter runs of this script, each scaled by what the same counter reads for one streaming kernel that
+# reads and writes 1 GiB (fetch x2.000, write x1.000).  The summary and its commands are in profiles/.  The figure belongs to
 # the kernel sources it was measured on: any change to them reports traffic as null until re-measured.
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/shape_panel.hip",
                  "paper_1802_04256_amd/csrc/shape_common.h", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "3cdd9b187e9f4577b3e909845dd5c40721d78f462ff639176c2fc55c40b49cd8", "bytes_per_step": 3.903e10}
+SHAPE_TRAFFIC = {"sources_sha256": "f38ea0490bade17caa386d69101722ba507a88ac8b4605db0c34497dcc9d24a0", "bytes_per_step": 3.4495e10}
 
 
 def log(*a):
