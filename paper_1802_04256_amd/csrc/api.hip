@@ -186,11 +186,9 @@ void rpim_plan_destroy(rpim_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   dfree(p->node_xyz0); dfree(p->gp_xyz); dfree(p->gp_wdet); dfree(p->gp_cell); dfree(p->d_gp_off); dfree(p->d_node_off);
-  dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
-  dfree(p->blk_col); dfree(p->blk_row); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
-  dfree(p->gp_order); dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
-  dfree(p->lu_off); dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->msym); dfree(p->pbar); dfree(p->dEs); dfree(p->dEg); dfree(p->dXs);
-  dfree(p->cell_ptr); dfree(p->cell_gp);
+  free_pattern(p);
+  dfree(p->R); dfree(p->dphi); dfree(p->dphi32);
+  dfree(p->lu); dfree(p->piv); dfree(p->gam); dfree(p->msym); dfree(p->pbar); dfree(p->dEs); dfree(p->dEg); dfree(p->dXs);
   dfree(p->status);
   for (int i = 0; i < 2 * RPIM_N_PHASES; ++i)
     if (p->ev[i]) (void)hipEventDestroy(p->ev[i]);
@@ -221,7 +219,7 @@ rpim_status rpim_rebuild_pattern(rpim_plan* p, const double* node_xyz, int64_t* 
   if ((row_ptr == nullptr) != (col_idx == nullptr)) return RPIM_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   RPIM_HIP(hipStreamSynchronize(s));
-  free_pattern(p);
+  p->built = false;  // the pattern arrays are rebuilt in place
   p->have_factors = false;
   ++p->factor_gen;
   RPIM_HIP(hipMemcpyAsync(p->node_xyz0, node_xyz, sizeof(double) * 3 * p->N, hipMemcpyDeviceToDevice, s));

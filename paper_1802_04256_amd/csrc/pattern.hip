@@ -333,42 +333,117 @@ __global__ void k_expand_cols(int64_t nblk, const int64_t* blk_ptr, const int32_
     for (int be = 0; be < 3; ++be) col_idx[9 * b + 3 * al * L + 3 * pos + be] = 3 * J + be;
 }
 
+// ---- buckets and packed-factor offsets (every rebuild) ------------------------
+// Bucket of each Gauss point (N = n + 4 rounded up to kBucketStep), its packed
+// factor size N^2, the bucket sizes and the smallest and largest support
+// (integer atomics: the totals do not depend on the order).
+__global__ void k_point_sizes(int64_t G, const int64_t* gp_ptr, int32_t* bkt, int64_t* nsq,
+                              unsigned long long* bcount, int* nrange) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int n = (int)(gp_ptr[g + 1] - gp_ptr[g]);
+  const int b = (n + 4 + kBucketStep - 1) / kBucketStep;
+  bkt[g] = b;
+  nsq[g] = (int64_t)(n + 4) * (n + 4);
+  atomicAdd(&bcount[b], 1ull);
+  atomicMin(&nrange[0], n);
+  atomicMax(&nrange[1], n);
+}
+
+constexpr int kOrderTile = 1024;  // Gauss points per tile of the bucket grouping
+
+// Points of tile t in each bucket, bucket-major: cnt[b * tiles + t].
+__global__ void __launch_bounds__(256) k_order_count(int64_t G, const int32_t* bkt, int64_t tiles, int32_t* cnt) {
+  __shared__ int c[kMaxBuckets];
+  for (int i = threadIdx.x; i < kMaxBuckets; i += blockDim.x) c[i] = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kOrderTile;
+  for (int i = threadIdx.x; i < kOrderTile; i += blockDim.x)
+    if (t0 + i < G) atomicAdd(&c[bkt[t0 + i]], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kMaxBuckets; b += blockDim.x) cnt[(int64_t)b * tiles + blockIdx.x] = c[b];
+}
+
+// One wave per tile: the tile's points, in ascending g, go to their bucket's
+// range from the tile's offset on, so each bucket lists its points in
+// ascending g.  Lane b < kMaxBuckets carries bucket b's next free slot.
+__global__ void __launch_bounds__(64) k_order_fill(int64_t G, const int32_t* bkt, int64_t tiles, const int64_t* off,
+                                                   int32_t* order) {
+  static_assert(kMaxBuckets <= 64, "one lane per bucket");
+  const int lane = threadIdx.x;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  long long mine = lane < kMaxBuckets ? off[(int64_t)lane * tiles + blockIdx.x] : 0;
+  const int64_t t0 = (int64_t)blockIdx.x * kOrderTile;
+  for (int r = 0; r < kOrderTile; r += 64) {
+    const int64_t g = t0 + r + lane;
+    const int b = g < G ? bkt[g] : -1;
+    for (int bb = 0; bb < kMaxBuckets; ++bb) {
+      const unsigned long long m = __ballot(b == bb);
+      if (m == 0) continue;  // uniform
+      const long long base = __shfl(mine, bb);
+      if (b == bb) order[base + __popcll(m & below)] = (int32_t)g;
+      if (lane == bb) mine += __popcll(m);
+    }
+  }
+}
+
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Device temporaries of one pattern build, freed on every exit path (the
-// stream is synchronised first, so no kernel still uses them).
-class Scratch {
+inline size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The temporaries of one pattern build, carved from one plan-owned buffer that
+// every rebuild reuses (no allocation or free on the rebuild path once sized).
+class Arena {
  public:
-  explicit Scratch(hipStream_t s) : s_(s) {}
-  ~Scratch() {
-    if (ptrs_.empty()) return;
-    (void)hipStreamSynchronize(s_);
-    for (void* q : ptrs_) (void)hipFree(q);
+  Arena(char* base, size_t cap) : base_(base), cap_(cap) {}
+  template <class T>
+  T* take(int64_t count) {
+    const size_t b = bytes<T>(count);
+    if (used_ + b > cap_) return nullptr;
+    T* q = reinterpret_cast<T*>(base_ + used_);
+    used_ += b;
+    return q;
   }
   template <class T>
-  rpim_status alloc(T** out, int64_t count) {
-    *out = nullptr;
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
-    if (e != hipSuccess) return hip_ok(e);
-    ptrs_.push_back(q);
-    *out = static_cast<T*>(q);
-    return RPIM_OK;
-  }
-  // hand a temporary over to the plan (not freed here)
-  template <class T>
-  void release(T* q) {
-    for (size_t i = 0; i < ptrs_.size(); ++i)
-      if (ptrs_[i] == (void*)q) {
-        ptrs_.erase(ptrs_.begin() + (long)i);
-        return;
-      }
+  static size_t bytes(int64_t count) {
+    return round256(sizeof(T) * (size_t)std::max<int64_t>(count, 1));
   }
 
  private:
-  hipStream_t s_;
-  std::vector<void*> ptrs_;
+  char* base_;
+  size_t cap_;
+  size_t used_ = 0;
 };
+
+rpim_status ensure_bytes(void** q, size_t* cap, size_t need) {
+  if (*q && *cap >= need) return RPIM_OK;
+  if (*q) (void)hipFree(*q);
+  *q = nullptr;
+  *cap = 0;
+  RPIM_HIP(hipMalloc(q, need));
+  *cap = need;
+  return RPIM_OK;
+}
+
+// Plan arrays whose size depends on the geometry: kept while large enough.
+template <class T>
+rpim_status reserve(T** q, int64_t* cap, int64_t count) {
+  if (*q && *cap >= count) return RPIM_OK;
+  if (*q) (void)hipFree(*q);
+  *q = nullptr;
+  *cap = 0;
+  RPIM_HIP(hipMalloc((void**)q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+  *cap = count;
+  return RPIM_OK;
+}
+
+// Plan arrays of fixed size (nodes or Gauss points): allocated once.
+template <class T>
+rpim_status once(T** q, int64_t count) {
+  if (*q) return RPIM_OK;
+  RPIM_HIP(hipMalloc((void**)q, sizeof(T) * (size_t)std::max<int64_t>(count, 1)));
+  return RPIM_OK;
+}
 
 template <class T>
 void dfree(T*& q) {
@@ -382,6 +457,10 @@ void free_pattern(rpim_plan* p) {
   dfree(p->gp_ptr); dfree(p->gp_nbr); dfree(p->inv_ptr); dfree(p->inv_key); dfree(p->blk_ptr);
   dfree(p->blk_col); dfree(p->blk_row); dfree(p->gp_order); dfree(p->lu_off);
   dfree(p->cell_ptr); dfree(p->cell_gp); dfree(p->row_lo); dfree(p->rbm_off); dfree(p->rbm);
+  if (p->pat_scratch) (void)hipFree(p->pat_scratch);
+  p->pat_scratch = nullptr;
+  p->cap_pat_scratch = 0;
+  p->cap_gp_nbr = p->cap_inv_key = p->cap_blk = p->cap_rbm = 0;
   p->built = false;
   p->buckets.clear();
 }
@@ -390,16 +469,16 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   const int M = p->n_models;
   const int64_t N = p->N, G = p->G;
   RPIM_HIP(hipStreamSynchronize(s));
-  free_pattern(p);  // arrays of an earlier (possibly failed) build
-  Scratch tmp(s);
+  p->built = false;
+  p->buckets.clear();
   rpim_status st = RPIM_OK;
 #define RPIM_TRY(x)                   \
   do {                                \
     if ((st = (x)) != RPIM_OK) return st; \
   } while (0)
   // bounding boxes -> bin grids (host)
-  double* d_bb = nullptr;
-  RPIM_TRY(tmp.alloc(&d_bb, 6 * M));
+  RPIM_TRY(ensure_bytes(&p->pat_scratch, &p->cap_pat_scratch, Arena::bytes<double>(6 * M)));
+  double* d_bb = Arena((char*)p->pat_scratch, p->cap_pat_scratch).take<double>(6 * M);
   hipLaunchKernelGGL(k_bbox, dim3(M), dim3(256), 0, s, X, (const int64_t*)p->d_node_off, d_bb);
   RPIM_HIP(hipGetLastError());
   std::vector<double> bb(6 * M);
@@ -429,17 +508,34 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     nbins += dims[0] * dims[1] * dims[2];
   }
   if (nbins >= INT32_MAX) return RPIM_E_RANGE;
-  BinGrid* d_grids = nullptr;
-  int32_t *node_bin = nullptr, *bin_cnt = nullptr, *bin_nodes = nullptr, *counts = nullptr;
-  int64_t* bin_start = nullptr;
-  double* bxyz = nullptr;
-  RPIM_TRY(tmp.alloc(&d_grids, M));
+  // every temporary of this build in one buffer (the bounding boxes are consumed)
+  const int64_t tiles = (G + kOrderTile - 1) / kOrderTile;
+  const size_t need = Arena::bytes<BinGrid>(M) + Arena::bytes<int32_t>(N) + Arena::bytes<int32_t>(nbins) +
+                      Arena::bytes<int64_t>(nbins + 1) + Arena::bytes<int32_t>(N) + Arena::bytes<double>(3 * N) +
+                      Arena::bytes<int32_t>(std::max<int64_t>(G, N)) + 3 * Arena::bytes<int32_t>(N) +
+                      Arena::bytes<int32_t>(G) + Arena::bytes<int64_t>(G) +
+                      Arena::bytes<int32_t>(kMaxBuckets * tiles) + Arena::bytes<int64_t>(kMaxBuckets * tiles + 1) +
+                      Arena::bytes<unsigned long long>(kMaxBuckets) + Arena::bytes<int>(2);
+  RPIM_TRY(ensure_bytes(&p->pat_scratch, &p->cap_pat_scratch, need));
+  Arena tmp((char*)p->pat_scratch, p->cap_pat_scratch);
+  BinGrid* d_grids = tmp.take<BinGrid>(M);
+  int32_t* node_bin = tmp.take<int32_t>(N);
+  int32_t* bin_cnt = tmp.take<int32_t>(nbins);
+  int64_t* bin_start = tmp.take<int64_t>(nbins + 1);
+  int32_t* bin_nodes = tmp.take<int32_t>(N);
+  double* bxyz = tmp.take<double>(3 * N);
+  int32_t* counts = tmp.take<int32_t>(std::max<int64_t>(G, N));
+  int32_t* inv_cnt = tmp.take<int32_t>(N);
+  int32_t* cursor = tmp.take<int32_t>(N);
+  int32_t* win_len = tmp.take<int32_t>(N);
+  int32_t* bkt = tmp.take<int32_t>(G);
+  int64_t* nsq = tmp.take<int64_t>(G);
+  int32_t* ocnt = tmp.take<int32_t>(kMaxBuckets * tiles);
+  int64_t* ooff = tmp.take<int64_t>(kMaxBuckets * tiles + 1);
+  unsigned long long* bcount = tmp.take<unsigned long long>(kMaxBuckets);
+  int* nrange = tmp.take<int>(2);
+  if (!nrange) return RPIM_E_STATE;  // the sizes above and the carving disagree (never)
   RPIM_HIP(hipMemcpyAsync(d_grids, grids.data(), sizeof(BinGrid) * M, hipMemcpyHostToDevice, s));
-  RPIM_TRY(tmp.alloc(&node_bin, N));
-  RPIM_TRY(tmp.alloc(&bin_cnt, nbins));
-  RPIM_TRY(tmp.alloc(&bin_start, nbins + 1));
-  RPIM_TRY(tmp.alloc(&bin_nodes, N));
-  RPIM_TRY(tmp.alloc(&bxyz, 3 * N));
   RPIM_HIP(hipMemsetAsync(bin_cnt, 0, sizeof(int32_t) * nbins, s));
   hipLaunchKernelGGL(k_bin_count, dim3(nblocks(N, 256)), dim3(256), 0, s, X, N, (const int64_t*)p->d_node_off,
                      M, (const BinGrid*)d_grids, node_bin, bin_cnt);
@@ -453,25 +549,23 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipGetLastError());
 
   // supports: count, scan, fill
-  RPIM_TRY(tmp.alloc(&counts, std::max<int64_t>(G, N)));
-  RPIM_HIP(hipMalloc((void**)&p->gp_ptr, sizeof(int64_t) * (G + 1)));
+  RPIM_TRY(once(&p->gp_ptr, G + 1));
   hipLaunchKernelGGL(k_support<false>, dim3(nblocks(G, 4)), dim3(256), 0, s, G, (const int64_t*)p->d_gp_off, M,
                      (const BinGrid*)d_grids, (const int64_t*)bin_start, (const int32_t*)bin_nodes,
                      (const double*)bxyz, (const double*)p->gp_xyz, counts, (const int64_t*)nullptr,
                      (int32_t*)nullptr, p->status);
   RPIM_HIP(hipGetLastError());
+  RPIM_TRY(exclusive_scan(counts, G, p->gp_ptr, s));
   DevStatus hst;
+  int64_t sum_n = 0;
   RPIM_HIP(hipMemcpyAsync(&hst, p->status, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipMemcpyAsync(&sum_n, p->gp_ptr + G, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipStreamSynchronize(s));
   if (hst.flags & kFlagRange) return RPIM_E_RANGE;
   if (hst.flags & kFlagSupport) return RPIM_E_SUPPORT;
-  RPIM_TRY(exclusive_scan(counts, G, p->gp_ptr, s));
-  std::vector<int64_t> gp_ptr_h(G + 1);
-  RPIM_HIP(hipMemcpyAsync(gp_ptr_h.data(), p->gp_ptr, sizeof(int64_t) * (G + 1), hipMemcpyDeviceToHost, s));
-  RPIM_HIP(hipStreamSynchronize(s));
-  p->sum_n = gp_ptr_h[G];
+  p->sum_n = sum_n;
   if (p->sum_n >= INT32_MAX) return RPIM_E_RANGE;
-  RPIM_HIP(hipMalloc((void**)&p->gp_nbr, sizeof(int32_t) * p->sum_n));
+  RPIM_TRY(reserve(&p->gp_nbr, &p->cap_gp_nbr, p->sum_n));
   hipLaunchKernelGGL(k_support<true>, dim3(nblocks(G, 4)), dim3(256), 0, s, G, (const int64_t*)p->d_gp_off, M,
                      (const BinGrid*)d_grids, (const int64_t*)bin_start, (const int32_t*)bin_nodes,
                      (const double*)bxyz, (const double*)p->gp_xyz, counts, (const int64_t*)p->gp_ptr,
@@ -479,18 +573,15 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipGetLastError());
 
   // inverse lists
-  int32_t *cursor = nullptr, *inv_cnt = nullptr;
-  RPIM_TRY(tmp.alloc(&inv_cnt, N));
-  RPIM_TRY(tmp.alloc(&cursor, N));
   RPIM_HIP(hipMemsetAsync(inv_cnt, 0, sizeof(int32_t) * N, s));
   hipLaunchKernelGGL(k_inv_count, dim3(nblocks(p->sum_n, 256)), dim3(256), 0, s, p->sum_n,
                      (const int32_t*)p->gp_nbr, inv_cnt);
-  RPIM_HIP(hipMalloc((void**)&p->inv_ptr, sizeof(int64_t) * (N + 1)));
+  RPIM_TRY(once(&p->inv_ptr, N + 1));
   RPIM_TRY(exclusive_scan(inv_cnt, N, p->inv_ptr, s));
   std::vector<int32_t> cnt_h(N);
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), inv_cnt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * N, s));
-  RPIM_HIP(hipMalloc((void**)&p->inv_key, sizeof(uint64_t) * p->sum_n));
+  RPIM_TRY(reserve(&p->inv_key, &p->cap_inv_key, p->sum_n));
   hipLaunchKernelGGL(k_inv_fill, dim3(nblocks(G, 256)), dim3(256), 0, s, G, (const int64_t*)p->gp_ptr,
                      (const int32_t*)p->gp_nbr, (const int64_t*)p->inv_ptr, cursor, p->inv_key);
   RPIM_HIP(hipGetLastError());
@@ -506,12 +597,9 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   RPIM_HIP(hipGetLastError());
 
   // node-block rows
-  int32_t *win_lo = nullptr, *win_len = nullptr, *blk_cnt = nullptr;
-  RPIM_HIP(hipMalloc((void**)&win_lo, sizeof(int32_t) * N));
-  p->row_lo = win_lo;  // plan-owned from here (the window start of each row)
-  RPIM_TRY(tmp.alloc(&win_len, N));
+  RPIM_TRY(once(&p->row_lo, N));  // the window start of each row
   hipLaunchKernelGGL(k_window, dim3((unsigned)N), dim3(256), 0, s, N, (const int64_t*)p->inv_ptr,
-                     (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, win_lo,
+                     (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr, (const int32_t*)p->gp_nbr, p->row_lo,
                      win_len);
   RPIM_HIP(hipGetLastError());
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), win_len, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
@@ -520,7 +608,7 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   for (int64_t i = 0; i < N; ++i) max_win = std::max<int64_t>(max_win, cnt_h[i]);
   if (max_win > kMaxWindow) return RPIM_E_RANGE;
   const int words = (int)((max_win + 31) / 32);
-  blk_cnt = counts;  // reuse (size >= N)
+  int32_t* blk_cnt = counts;  // reuse (size >= N)
   // per-row rank bitmaps: word offsets from the window lengths
   {
     std::vector<int64_t> off(N + 1, 0);
@@ -532,16 +620,17 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     }
     p->rbm_words = off[N];
     p->max_row_words = mw;
-    RPIM_HIP(hipMalloc((void**)&p->rbm_off, sizeof(int64_t) * (N + 1)));
-    RPIM_HIP(hipMalloc((void**)&p->rbm, sizeof(uint2) * std::max<int64_t>(off[N], 1)));
+    RPIM_TRY(once(&p->rbm_off, N + 1));
+    RPIM_TRY(reserve(&p->rbm, &p->cap_rbm, std::max<int64_t>(off[N], 1)));
     RPIM_HIP(hipMemcpyAsync(p->rbm_off, off.data(), sizeof(int64_t) * (N + 1), hipMemcpyHostToDevice, s));
+    RPIM_HIP(hipStreamSynchronize(s));  // off is a host temporary
   }
   hipLaunchKernelGGL(k_blocks_union, dim3((unsigned)N), dim3(256), sizeof(unsigned) * std::max(words, 1), s,
                      (const int64_t*)p->inv_ptr, (const uint64_t*)p->inv_key, (const int64_t*)p->gp_ptr,
-                     (const int32_t*)p->gp_nbr, (const int32_t*)win_lo, (const int32_t*)win_len, blk_cnt,
+                     (const int32_t*)p->gp_nbr, (const int32_t*)p->row_lo, (const int32_t*)win_len, blk_cnt,
                      (const int64_t*)p->rbm_off, p->rbm);
   RPIM_HIP(hipGetLastError());
-  RPIM_HIP(hipMalloc((void**)&p->blk_ptr, sizeof(int64_t) * (N + 1)));
+  RPIM_TRY(once(&p->blk_ptr, N + 1));
   RPIM_TRY(exclusive_scan(blk_cnt, N, p->blk_ptr, s));
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), blk_cnt, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
   int64_t nblk = 0;
@@ -551,48 +640,62 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
   p->nnz = 9 * nblk;
   p->max_row_blocks = 0;
   for (int64_t i = 0; i < N; ++i) p->max_row_blocks = std::max<int64_t>(p->max_row_blocks, cnt_h[i]);
-  RPIM_HIP(hipMalloc((void**)&p->blk_col, sizeof(int32_t) * nblk));
-  RPIM_HIP(hipMalloc((void**)&p->blk_row, sizeof(int32_t) * nblk));
+  if (p->cap_blk < nblk || !p->blk_col || !p->blk_row) {  // blk_col and blk_row share one capacity
+    dfree(p->blk_col);
+    dfree(p->blk_row);
+    p->cap_blk = 0;
+    RPIM_TRY(once(&p->blk_col, nblk));
+    RPIM_TRY(once(&p->blk_row, nblk));
+    p->cap_blk = nblk;
+  }
   int32_t* upper = inv_cnt;  // reuse (size N): columns J >= I of each row
-  hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)N), dim3(256), 0, s, (const int32_t*)win_lo,
+  hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)N), dim3(256), 0, s, (const int32_t*)p->row_lo,
                      (const int64_t*)p->blk_ptr, p->blk_col, p->blk_row, (const int64_t*)p->rbm_off, p->rbm, upper);
   RPIM_HIP(hipGetLastError());
+
+  // buckets by padded moment-matrix size, packed-factor offsets and the
+  // bucket-grouped point order, on the device
+  static const int kNrangeInit[2] = {INT_MAX, 0};
+  RPIM_HIP(hipMemsetAsync(bcount, 0, sizeof(unsigned long long) * kMaxBuckets, s));
+  RPIM_HIP(hipMemcpyAsync(nrange, kNrangeInit, sizeof(kNrangeInit), hipMemcpyHostToDevice, s));
+  RPIM_TRY(once(&p->lu_off, G + 1));
+  RPIM_TRY(once(&p->gp_order, G));
+  if (G > 0) {
+    hipLaunchKernelGGL(k_point_sizes, dim3(nblocks(G, 256)), dim3(256), 0, s, G, (const int64_t*)p->gp_ptr, bkt, nsq,
+                       bcount, nrange);
+    RPIM_HIP(hipGetLastError());
+    RPIM_TRY(exclusive_scan64(nsq, G, p->lu_off, s));
+    hipLaunchKernelGGL(k_order_count, dim3((unsigned)tiles), dim3(256), 0, s, G, (const int32_t*)bkt, tiles, ocnt);
+    RPIM_HIP(hipGetLastError());
+    RPIM_TRY(exclusive_scan(ocnt, kMaxBuckets * tiles, ooff, s));
+    hipLaunchKernelGGL(k_order_fill, dim3((unsigned)tiles), dim3(64), 0, s, G, (const int32_t*)bkt, tiles,
+                       (const int64_t*)ooff, p->gp_order);
+    RPIM_HIP(hipGetLastError());
+  } else {
+    RPIM_HIP(hipMemsetAsync(p->lu_off, 0, sizeof(int64_t), s));
+  }
+  // the host needs the bucket sizes (one launch per bucket) and the widest rows
+  unsigned long long bc[kMaxBuckets];
+  int nr[2];
+  int64_t lu_total = 0;
   RPIM_HIP(hipMemcpyAsync(cnt_h.data(), upper, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipMemcpyAsync(bc, bcount, sizeof(bc), hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipMemcpyAsync(nr, nrange, sizeof(nr), hipMemcpyDeviceToHost, s));
+  RPIM_HIP(hipMemcpyAsync(&lu_total, p->lu_off + G, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RPIM_HIP(hipStreamSynchronize(s));
   p->max_row_upper = 0;
   for (int64_t i = 0; i < N; ++i) p->max_row_upper = std::max<int64_t>(p->max_row_upper, cnt_h[i]);
-
-  // buckets by padded moment-matrix size, and LU offsets (host, from gp_ptr)
-  p->min_n = INT32_MAX;
-  p->max_n = 0;
-  const int nb = (kMaxSupport + 4) / kBucketStep + 1;
-  std::vector<int64_t> bcount(nb, 0);
-  std::vector<int64_t> lu_off_h(G + 1, 0);
-  for (int64_t g = 0; g < G; ++g) {
-    const int n = (int)(gp_ptr_h[g + 1] - gp_ptr_h[g]);
-    p->min_n = std::min(p->min_n, n);
-    p->max_n = std::max(p->max_n, n);
-    bcount[(n + 4 + kBucketStep - 1) / kBucketStep]++;
-    lu_off_h[g + 1] = lu_off_h[g] + (int64_t)(n + 4) * (n + 4);  // packed multipliers and U
-  }
-  p->lu_doubles = lu_off_h[G];
-  p->buckets.clear();
-  std::vector<int64_t> bstart(nb, 0);
+  p->min_n = G > 0 ? nr[0] : 0;
+  p->max_n = G > 0 ? nr[1] : 0;
+  p->lu_doubles = lu_total;
   int64_t acc = 0;
-  for (int b = 0; b < nb; ++b) {
-    bstart[b] = acc;
-    if (bcount[b]) p->buckets.push_back(Bucket{b * kBucketStep, acc, bcount[b]});
-    acc += bcount[b];
+  for (int b = 0; b < kMaxBuckets; ++b) {
+    if (bc[b]) p->buckets.push_back(Bucket{b * kBucketStep, acc, (int64_t)bc[b]});
+    acc += (int64_t)bc[b];
   }
-  std::vector<int32_t> order(G);
-  for (int64_t g = 0; g < G; ++g) {
-    const int n = (int)(gp_ptr_h[g + 1] - gp_ptr_h[g]);
-    order[bstart[(n + 4 + kBucketStep - 1) / kBucketStep]++] = (int32_t)g;
-  }
-  RPIM_HIP(hipMalloc((void**)&p->gp_order, sizeof(int32_t) * std::max<int64_t>(G, 1)));
-  RPIM_HIP(hipMemcpyAsync(p->gp_order, order.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
-  // cell -> Gauss point lists (ascending g) for the deterministic dE reduction
-  {
+  // cell -> Gauss point lists (ascending g) for the deterministic dE reduction:
+  // they depend on the cells only, so the first build makes them for good
+  if (!p->cell_ptr) {
     std::vector<int32_t> cell_h(G);
     RPIM_HIP(hipMemcpyAsync(cell_h.data(), p->gp_cell, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
     RPIM_HIP(hipStreamSynchronize(s));
@@ -605,15 +708,12 @@ rpim_status build_pattern_device(rpim_plan* p, const double* X, hipStream_t s) {
     std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
     std::vector<int32_t> cgp(std::max<int64_t>(G, 1));
     for (int64_t g = 0; g < G; ++g) cgp[fill[cell_h[g]]++] = (int32_t)g;
-    RPIM_HIP(hipMalloc((void**)&p->cell_ptr, sizeof(int64_t) * (p->C + 1)));
-    RPIM_HIP(hipMalloc((void**)&p->cell_gp, sizeof(int32_t) * std::max<int64_t>(G, 1)));
+    RPIM_TRY(once(&p->cell_ptr, p->C + 1));
+    RPIM_TRY(once(&p->cell_gp, G));
     RPIM_HIP(hipMemcpyAsync(p->cell_ptr, cptr.data(), sizeof(int64_t) * (p->C + 1), hipMemcpyHostToDevice, s));
     RPIM_HIP(hipMemcpyAsync(p->cell_gp, cgp.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s));
     RPIM_HIP(hipStreamSynchronize(s));
   }
-  RPIM_HIP(hipMalloc((void**)&p->lu_off, sizeof(int64_t) * (G + 1)));
-  RPIM_HIP(hipMemcpyAsync(p->lu_off, lu_off_h.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
-  RPIM_HIP(hipStreamSynchronize(s));
 #undef RPIM_TRY
   p->built = true;
   return RPIM_OK;

@@ -94,6 +94,11 @@ struct rpim_plan {
   // solver kernel per bucket (index nmax / kBucketStep): RPIM_SOLVER_* from rpim.h
   int8_t solver_kind[rpim::kMaxBuckets] = {};
   int32_t* gp_order = nullptr;   // [G] Gauss points grouped by bucket
+  // rebuild reuse: capacities of the pattern arrays whose size follows the
+  // geometry, and one buffer for the temporaries of a build
+  int64_t cap_gp_nbr = 0, cap_inv_key = 0, cap_blk = 0, cap_rbm = 0;
+  void* pat_scratch = nullptr;
+  size_t cap_pat_scratch = 0;
 
   // assembly workspace
   double* R = nullptr;           // [nblk] radial basis per node pair
@@ -165,6 +170,7 @@ inline rpim_status ensure(T** p, int64_t* cap, int64_t count) {
 // --- scan.hip ----------------------------------------------------------------
 // Exclusive prefix sum of n int32 counts into int64 offsets out[n+1].
 rpim_status exclusive_scan(const int32_t* counts, int64_t n, int64_t* out, hipStream_t s);
+rpim_status exclusive_scan64(const int64_t* values, int64_t n, int64_t* out, hipStream_t s);
 
 // --- pattern.hip -------------------------------------------------------------
 // Builds supports, pattern, buckets and lists into the plan; frees the plan's

@@ -1,4 +1,4 @@
-// Exclusive prefix sums (int32 counts -> int64 offsets[n+1]) in three passes:
+// Exclusive prefix sums (int32 or int64 values -> int64 offsets[n+1]) in three passes:
 // per-tile totals, a scan of the totals (recursively), then each tile rescans
 // and adds its base.  Used to size supports, inverse lists, bins and rows.
 #include "rpim_internal.h"
@@ -92,6 +92,10 @@ rpim_status scan_impl(const T* in, int64_t n, int64_t* out, hipStream_t s) {
 
 rpim_status exclusive_scan(const int32_t* counts, int64_t n, int64_t* out, hipStream_t s) {
   return scan_impl<int32_t>(counts, n, out, s);
+}
+
+rpim_status exclusive_scan64(const int64_t* values, int64_t n, int64_t* out, hipStream_t s) {
+  return scan_impl<int64_t>(values, n, out, s);
 }
 
 }  // namespace rpim
