@@ -52,6 +52,7 @@ def lib():
         L.orcl_dot_q.argtypes = [vp, dp, dp, d, dp, i64p, i64, dp]
         L.orcl_body_force.argtypes = [vp, dp, dp, dp]
         L.orcl_gauss_stress.argtypes = [vp, dp, dp, d, dp, dp]
+        L.orcl_set_shape.argtypes = [vp, C.c_int]
         L.orcl_pow_cr.restype = d
         L.orcl_pow_cr.argtypes = [d, d]
         L.orcl_pow_fallbacks.restype = C.c_long
@@ -79,7 +80,9 @@ def _check(st, what):
 class OracleModel:
     """Serial FP64 RPIM assembly of one model (or a block-diagonal batch)."""
 
-    def __init__(self, prob):
+    SHAPES = {"rpim": 0, "mls": 1, "shepard": 2}
+
+    def __init__(self, prob, shape="rpim"):
         self.prob = prob
         L = lib()
         self._keep = [np.ascontiguousarray(prob.node_xyz, np.float64),
@@ -91,6 +94,7 @@ class OracleModel:
                                      prob.support_radius, prob.alpha_c, prob.d_c, prob.q)
         if not self.h:
             raise OracleError(E_ARG, "create")
+        _check(L.orcl_set_shape(self.h, self.SHAPES[shape]), "set_shape")
         self.nnz = None
         self.sum_n = None
 

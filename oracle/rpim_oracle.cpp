@@ -51,6 +51,10 @@
 //
 // An extended-precision (__float128) evaluation of the same formulas, with the
 // supports frozen, backs the finite-difference gradient checks.
+//
+// Moving-least-squares and Shepard shape functions (Sec. 4) can replace the
+// RPIM ones for assembly, body force and stresses; their operation order
+// (M1-M6) is written out above gp_mls.
 
 #include <quadmath.h>
 
@@ -127,6 +131,7 @@ struct Model {
   std::vector<double> node, gp, wdet;
   std::vector<int32_t> cell;
   double ds = 0, alpha_c = 0, dc = 0, q = 0;
+  int shape_kind = 0;  // 0 RPIM, 1 moving least squares (linear basis), 2 Shepard
   bool built = false;
   // supports (C3): gp_ptr[G+1], gp_nbr[sum n]
   std::vector<int64_t> gp_ptr;
@@ -273,6 +278,148 @@ void lu_solve(int Nn, const std::vector<double>& lu, const std::vector<int>& piv
   }
 }
 
+// ---------------------------------------------------------------------------
+// Moving-least-squares shape functions (named in Sec. 4 as the package's next
+// shape functions): linear basis (M = 4) or constant basis (M = 1, Shepard's
+// functions), with the cubic-spline weight over the support radius d_s.
+//   M1  d = x_g - x_i per component; s = fma(dz,dz, fma(dy,dy, dx*dx));
+//       r = sqrt(s) / d_s; basis p = [1, x_i - x_g] (M = 4) or [1] (M = 1).
+//   M2  r2 = r*r; r <= 1/2: W = (fl(2/3) - 4*r2) + (4*r2)*r, Wr = fma(12, r, -8);
+//       1/2 < r <= 1: W = ((fl(4/3) - 4*r) + 4*r2) - fl(4/3)*(r2*r),
+//       Wr = (8 - 4/r) - 4*r; otherwise W = Wr = 0.  Wr = W'(r)/r, and the
+//       weight's gradient at x_g is w_k = (Wr*d_k) / fl(d_s*d_s).
+//   M3  A_jl (j <= l) = +0 + t_1 + t_2 + ... in ascending support order,
+//       t = (W*p_j)*p_l; the derivative matrices A^k likewise with
+//       t = (w_k*p_j)*p_l; A_lj = A_jl.
+//   M4  A = LU by C6 (singular if |u_kk| <= M*eps*max|A|); gamma = A^-1 e_0:
+//       interchanges applied to the right-hand side in step order, forward
+//       b_r = fma(-l_rk, b_k, b_r), back substitution by C7.
+//   M5  gamma_k = A^-1 rhs with the same factors, rhs_j = [j == k+1] - s_j,
+//       s_j the fma chain over l ascending of A^k_jl gamma_l from +0 (the
+//       term [j == k+1] only exists for M = 4).
+//   M6  c = gamma^T p = fma(g3,p3, fma(g2,p2, fma(g1,p1, g0))) (g0 for M = 1),
+//       c_k likewise from gamma_k; phi = W*c, dphi_k = fma(W, c_k, w_k*c).
+// ---------------------------------------------------------------------------
+int gp_mls(const Model& m, const double* X, int64_t g, int M, std::vector<double>& phi, std::vector<double>& dphi) {
+  const int64_t b0 = m.gp_ptr[g];
+  const int n = (int)(m.gp_ptr[g + 1] - b0);
+  const int32_t* S = &m.gp_nbr[b0];
+  const double* xg = &m.gp[3 * g];
+  const double C23 = 2.0 / 3.0, C43 = 4.0 / 3.0;
+  const double dw2 = m.ds * m.ds;
+  std::vector<double> W(n), wk(3 * (size_t)n), P(4 * (size_t)n);
+  for (int a = 0; a < n; ++a) {  // M1, M2
+    const double* xi = &X[3 * (int64_t)S[a]];
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = xg[k] - xi[k];
+    const double s = std::fma(d[2], d[2], std::fma(d[1], d[1], d[0] * d[0]));
+    const double r = std::sqrt(s) / m.ds;
+    const double r2 = r * r;
+    double Wa = 0.0, Wr = 0.0;
+    if (r <= 0.5) {
+      Wa = (C23 - 4.0 * r2) + (4.0 * r2) * r;
+      Wr = std::fma(12.0, r, -8.0);
+    } else if (r <= 1.0) {
+      Wa = ((C43 - 4.0 * r) + 4.0 * r2) - C43 * (r2 * r);
+      Wr = (8.0 - 4.0 / r) - 4.0 * r;
+    }
+    W[a] = Wa;
+    for (int k = 0; k < 3; ++k) wk[3 * a + k] = (Wr * d[k]) / dw2;
+    P[4 * a] = 1.0;
+    for (int k = 0; k < 3; ++k) P[4 * a + 1 + k] = xi[k] - xg[k];
+  }
+  double A[4][4] = {}, Ak[3][4][4] = {};
+  for (int j = 0; j < M; ++j)  // M3
+    for (int l = j; l < M; ++l) {
+      double s0 = 0.0, s1[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < n; ++a) {
+        s0 = s0 + (W[a] * P[4 * a + j]) * P[4 * a + l];
+        for (int k = 0; k < 3; ++k) s1[k] = s1[k] + (wk[3 * a + k] * P[4 * a + j]) * P[4 * a + l];
+      }
+      A[j][l] = A[l][j] = s0;
+      for (int k = 0; k < 3; ++k) Ak[k][j][l] = Ak[k][l][j] = s1[k];
+    }
+  double LU[4][4];  // M4
+  double mx = 0.0;
+  for (int j = 0; j < M; ++j)
+    for (int l = 0; l < M; ++l) {
+      LU[j][l] = A[j][l];
+      mx = std::max(mx, std::fabs(A[j][l]));
+    }
+  const double tiny = ((double)M * DBL_EPSILON) * mx;
+  int piv[4];
+  for (int k = 0; k < M; ++k) {
+    int p = k;
+    double best = std::fabs(LU[k][k]);
+    for (int r = k + 1; r < M; ++r) {
+      const double v = std::fabs(LU[r][k]);
+      if (v > best) { best = v; p = r; }
+    }
+    piv[k] = p;
+    if (!(best > tiny)) return E_SINGULAR;
+    if (p != k)
+      for (int c = 0; c < M; ++c) std::swap(LU[k][c], LU[p][c]);
+    for (int r = k + 1; r < M; ++r) {
+      const double l = LU[r][k] / LU[k][k];
+      LU[r][k] = l;
+      for (int c = k + 1; c < M; ++c) LU[r][c] = std::fma(-l, LU[k][c], LU[r][c]);
+    }
+  }
+  const auto solve = [&](double* b) {
+    for (int k = 0; k < M; ++k)
+      if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+    for (int k = 0; k < M; ++k)
+      for (int r = k + 1; r < M; ++r) b[r] = std::fma(-LU[r][k], b[k], b[r]);
+    for (int k = M - 1; k >= 0; --k) {
+      b[k] = b[k] / LU[k][k];
+      for (int r = 0; r < k; ++r) b[r] = std::fma(-LU[r][k], b[k], b[r]);
+    }
+  };
+  double gam[4] = {1.0, 0.0, 0.0, 0.0};
+  solve(gam);
+  double gk[3][4];
+  for (int k = 0; k < 3; ++k) {  // M5
+    for (int j = 0; j < M; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < M; ++l) s = std::fma(Ak[k][j][l], gam[l], s);
+      gk[k][j] = (j == k + 1 ? 1.0 : 0.0) - s;
+    }
+    solve(gk[k]);
+  }
+  phi.assign(n, 0.0);
+  dphi.assign(3 * (size_t)n, 0.0);
+  for (int a = 0; a < n; ++a) {  // M6
+    const double* pa = &P[4 * a];
+    double c = gam[0];
+    if (M == 4) c = std::fma(gam[3], pa[3], std::fma(gam[2], pa[2], std::fma(gam[1], pa[1], c)));
+    phi[a] = W[a] * c;
+    for (int k = 0; k < 3; ++k) {
+      double ck = gk[k][0];
+      if (M == 4) ck = std::fma(gk[k][3], pa[3], std::fma(gk[k][2], pa[2], std::fma(gk[k][1], pa[1], ck)));
+      dphi[3 * a + k] = std::fma(W[a], ck, wk[3 * a + k] * c);
+    }
+  }
+  return OK;
+}
+
+// Shape functions of point g under the model's kind: phi[a] (RPIM: only when
+// want_phi, from the value right-hand side) and dphi[3a+k].
+int point_shapes(const Model& m, const double* X, int64_t g, bool want_phi, std::vector<double>& phi,
+                 std::vector<double>& dphi) {
+  if (m.shape_kind != 0) return gp_mls(m, X, g, m.shape_kind == 1 ? 4 : 1, phi, dphi);
+  std::vector<double> sol;
+  const int st = gp_solve<double>(m, X, g, want_phi ? 4 : 3, sol);
+  if (st != OK) return st;
+  const int n = (int)(m.gp_ptr[g + 1] - m.gp_ptr[g]), Nn = n + 4;
+  phi.assign(n, 0.0);
+  dphi.assign(3 * (size_t)n, 0.0);
+  for (int a = 0; a < n; ++a) {
+    if (want_phi) phi[a] = sol[(size_t)3 * Nn + a];
+    for (int k = 0; k < 3; ++k) dphi[3 * a + k] = sol[(size_t)k * Nn + a];
+  }
+  return OK;
+}
+
 // Isotropic elasticity constants for E = 1 (C8), evaluated left to right.
 void lame_hat(double nu, double* lam, double* mu) {
   double onep = 1.0 + nu;
@@ -300,6 +447,15 @@ void* orcl_model_create(int64_t N, const double* node_xyz, int64_t G, const doub
 }
 
 void orcl_model_destroy(void* h) { delete (Model*)h; }
+
+// Shape functions of the model: 0 RPIM (default), 1 moving least squares with a
+// linear basis, 2 Shepard's functions (constant basis); both MLS kinds use the
+// cubic-spline weight over the support radius.  The adjoint is RPIM only.
+int orcl_set_shape(void* h, int kind) {
+  if (!h || kind < 0 || kind > 2) return E_ARG;
+  ((Model*)h)->shape_kind = kind;
+  return OK;
+}
 
 // Support search (brute force over all nodes, ascending id: C2, C3) and the
 // node-block pattern: cols(I) = union of S_g over Gauss points g with I in S_g.
@@ -372,13 +528,13 @@ int orcl_shape(void* h, int64_t g, const double* node_xyz, double* phi, double* 
   Model& m = *(Model*)h;
   if (!m.built || g < 0 || g >= m.G) return E_ARG;
   const double* X = node_xyz ? node_xyz : m.node.data();
-  std::vector<double> sol;
-  int st = gp_solve<double>(m, X, g, 4, sol);
+  std::vector<double> ph, dph;
+  int st = point_shapes(m, X, g, true, ph, dph);
   if (st != OK) return st;
-  const int n = (int)(m.gp_ptr[g + 1] - m.gp_ptr[g]), Nn = n + 4;
+  const int n = (int)(m.gp_ptr[g + 1] - m.gp_ptr[g]);
   for (int a = 0; a < n; ++a) {
-    if (phi) phi[a] = sol[(size_t)3 * Nn + a];
-    for (int k = 0; k < 3; ++k) dphi[3 * a + k] = sol[(size_t)k * Nn + a];
+    if (phi) phi[a] = ph[a];
+    for (int k = 0; k < 3; ++k) dphi[3 * a + k] = dph[3 * a + k];
   }
   return OK;
 }
@@ -410,20 +566,20 @@ int orcl_assemble(void* h, const double* node_xyz, const double* cell_E, double 
   lame_hat(nu, &lam, &mu);
   const int64_t count = gps ? n_gps : m.G;
   if (first_bad_gp) *first_bad_gp = -1;
-  std::vector<double> sol;
+  std::vector<double> phi, dphi;
   for (int64_t it = 0; it < count; ++it) {
     const int64_t g = gps ? gps[it] : it;
-    int st = gp_solve<double>(m, X, g, 3, sol);
+    int st = point_shapes(m, X, g, false, phi, dphi);
     if (st != OK) { if (first_bad_gp) *first_bad_gp = g; return st; }
     const int64_t b0 = m.gp_ptr[g];
-    const int n = (int)(m.gp_ptr[g + 1] - b0), Nn = n + 4;
+    const int n = (int)(m.gp_ptr[g + 1] - b0);
     const int32_t* S = &m.gp_nbr[b0];
     const double c = m.wdet[g] * cell_E[m.cell[g]];
     const double lc = c * lam, mc = c * mu;
     for (int a = 0; a < n; ++a) {
-      const double pa[3] = {sol[a], sol[(size_t)Nn + a], sol[(size_t)2 * Nn + a]};
+      const double pa[3] = {dphi[3 * a], dphi[3 * a + 1], dphi[3 * a + 2]};
       for (int b = 0; b < n; ++b) {
-        const double pb[3] = {sol[b], sol[(size_t)Nn + b], sol[(size_t)2 * Nn + b]};
+        const double pb[3] = {dphi[3 * b], dphi[3 * b + 1], dphi[3 * b + 2]};
         for (int al = 0; al < 3; ++al)
           for (int be = 0; be < 3; ++be) {
             int64_t pos = find_col(row_ptr.data(), col_idx.data(), 3 * (int64_t)S[a] + al, 3 * S[b] + be);
@@ -467,14 +623,14 @@ int orcl_body_force(void* h, const double* node_xyz, const double* gp_force, dou
   if (!m.built) return E_STATE;
   const double* X = node_xyz ? node_xyz : m.node.data();
   std::fill(f, f + 3 * m.N, 0.0);
-  std::vector<double> sol;
+  std::vector<double> phi, dphi;
   for (int64_t g = 0; g < m.G; ++g) {
-    int st = gp_solve<double>(m, X, g, 4, sol);
+    int st = point_shapes(m, X, g, true, phi, dphi);
     if (st != OK) return st;
     const int64_t b0 = m.gp_ptr[g];
-    const int n = (int)(m.gp_ptr[g + 1] - b0), Nn = n + 4;
+    const int n = (int)(m.gp_ptr[g + 1] - b0);
     for (int a = 0; a < n; ++a) {
-      const double c = m.wdet[g] * sol[(size_t)3 * Nn + a];
+      const double c = m.wdet[g] * phi[a];
       for (int k = 0; k < 3; ++k) {
         const int64_t d = 3 * (int64_t)m.gp_nbr[b0 + a] + k;
         f[d] = f[d] + c * gp_force[3 * g + k];
@@ -498,17 +654,17 @@ int orcl_gauss_stress(void* h, const double* node_xyz, const double* cell_E, dou
   const double* X = node_xyz ? node_xyz : m.node.data();
   double lam, mu;
   lame_hat(nu, &lam, &mu);
-  std::vector<double> sol;
+  std::vector<double> phi, dphi;
   for (int64_t g = 0; g < m.G; ++g) {
-    int st = gp_solve<double>(m, X, g, 3, sol);
+    int st = point_shapes(m, X, g, false, phi, dphi);
     if (st != OK) return st;
     const int64_t b0 = m.gp_ptr[g];
-    const int n = (int)(m.gp_ptr[g + 1] - b0), Nn = n + 4;
+    const int n = (int)(m.gp_ptr[g + 1] - b0);
     double H[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     for (int a = 0; a < n; ++a) {
       const int64_t I = m.gp_nbr[b0 + a];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) H[i][j] = std::fma(u[3 * I + i], sol[(size_t)j * Nn + a], H[i][j]);
+        for (int j = 0; j < 3; ++j) H[i][j] = std::fma(u[3 * I + i], dphi[3 * a + j], H[i][j]);
     }
     double e[3][3];
     for (int i = 0; i < 3; ++i)
@@ -567,7 +723,7 @@ int orcl_penalty(const int64_t* row_ptr, const int32_t* col_idx, void* K_vals, i
 int orcl_assemble_backward(void* h, const double* node_xyz, const double* cell_E, double nu,
                            const double* Kbar, const int64_t* gps, int64_t n_gps, double* dE, double* dX) {
   Model& m = *(Model*)h;
-  if (!m.built) return E_STATE;
+  if (!m.built || m.shape_kind != 0) return E_STATE;
   const double* X = node_xyz ? node_xyz : m.node.data();
   const int64_t ndof = 3 * m.N;
   std::vector<int64_t> row_ptr(ndof + 1);
@@ -680,7 +836,7 @@ int orcl_assemble_backward(void* h, const double* node_xyz, const double* cell_E
 int orcl_dot_q(void* h, const double* node_xyz, const double* cell_E, double nu, const double* Kbar,
                const int64_t* gps, int64_t n_gps, double* out_hi_lo) {
   Model& m = *(Model*)h;
-  if (!m.built) return E_STATE;
+  if (!m.built || m.shape_kind != 0) return E_STATE;
   const int64_t ndof = 3 * m.N;
   std::vector<int64_t> row_ptr(ndof + 1);
   std::vector<int32_t> col_idx(9 * m.blk_col.size());
