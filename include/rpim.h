@@ -289,6 +289,24 @@ rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
 enum { RPIM_SOLVER_AUTO = 0, RPIM_SOLVER_LDS = 1, RPIM_SOLVER_WINDOW = 2, RPIM_SOLVER_PANEL = 3 };
 rpim_status rpim_set_solver(rpim_plan* plan, int nmax, int kind);
 
+/* Shape functions of the plan (GeoMFree3D Sec. 4 names moving least squares
+ * as the package's next shape functions):
+ *   RPIM_SHAPE_RPIM     radial point interpolation (default; the path above)
+ *   RPIM_SHAPE_MLS      moving least squares, linear basis [1, x - x_g]
+ *   RPIM_SHAPE_SHEPARD  Shepard's functions (moving least squares with the
+ *                       constant basis)
+ * Both moving-least-squares kinds use the cubic-spline weight over the
+ * support radius (one radius for the whole plan, else RPIM_E_ARG from
+ * rpim_assemble) and the supports of the plan; rpim_assemble then forms the
+ * gradients with one 4 x 4 (or 1 x 1) moment matrix per Gauss point instead
+ * of the RPIM solve, and assembles K from them exactly as for RPIM.  With
+ * these kinds keep_factors has no effect, rpim_assemble_backward returns
+ * RPIM_E_STATE, and rpim_shape_values evaluates the values directly (no kept
+ * factors needed).  Changing the kind drops kept factors.  RPIM_E_ARG for an
+ * unknown kind. */
+enum { RPIM_SHAPE_RPIM = 0, RPIM_SHAPE_MLS = 1, RPIM_SHAPE_SHEPARD = 2 };
+rpim_status rpim_set_shape_functions(rpim_plan* plan, int kind);
+
 /* Identifier of the LU factors the plan currently keeps for the backward: a
  * new positive value after each rpim_assemble with keep_factors = 1, 0 once
  * they are gone (an assembly without keep_factors, rpim_autotune or

@@ -94,6 +94,7 @@ def lib():
         L.rpim_autotune.argtypes = [vp, vp, vp, d, i32, vp, vp, C.POINTER(_Tuning)]
         L.rpim_set_gather_waves.argtypes = [vp, i32, i32]
         L.rpim_set_solver.argtypes = [vp, i32, i32]
+        L.rpim_set_shape_functions.argtypes = [vp, i32]
         L.rpim_shape_values.argtypes = [vp, vp, vp, vp]
         L.rpim_body_force.argtypes = [vp, vp, vp, vp, vp]
         L.rpim_gauss_stress.argtypes = [vp, vp, d, vp, vp, vp]
@@ -110,7 +111,7 @@ def lib():
                   "rpim_profile_read", "rpim_autotune", "rpim_set_gather_waves", "rpim_set_solver",
                   "rpim_factor_generation", "rpim_apply_penalty_bc_noalloc",
                   "rpim_solve_pcg", "rpim_tuning_cache_save", "rpim_tuning_cache_load",
-                  "rpim_shape_values", "rpim_body_force", "rpim_gauss_stress"):
+                  "rpim_shape_values", "rpim_body_force", "rpim_gauss_stress", "rpim_set_shape_functions"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -266,6 +267,12 @@ class Plan:
         _check(lib().rpim_set_gather_waves(self._h, _precision(precision), int(waves)), "rpim_set_gather_waves")
 
     SOLVERS = {"auto": 0, "lds": 1, "window": 2, "panel": 3}
+    SHAPES = {"rpim": 0, "mls": 1, "shepard": 2}
+
+    def set_shape_functions(self, kind):
+        """'rpim' (default), 'mls' (linear basis) or 'shepard': the shape functions of later assemblies."""
+        k = self.SHAPES[kind] if isinstance(kind, str) else int(kind)
+        _check(lib().rpim_set_shape_functions(self._h, k), "rpim_set_shape_functions")
 
     def set_solver(self, kind, nmax: int = 0):
         """Moment-matrix solver kernel for the bucket of padded size nmax (0: all buckets)."""

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librpim.so")
-SOURCES = ["api.hip", "scan.hip", "pattern.hip", "assemble.hip", "shape_reg.hip", "shape_panel.hip", "backward.hip", "penalty.hip", "solve.hip", "post.hip"]
+SOURCES = ["api.hip", "scan.hip", "pattern.hip", "assemble.hip", "shape_reg.hip", "shape_panel.hip", "backward.hip", "penalty.hip", "solve.hip", "post.hip", "mls.hip"]
 
 
 def hipcc() -> str:

@@ -256,13 +256,24 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
   rpim_status st;
   if ((st = ensure(&p->R, &p->cap_R, p->nblk)) || (st = ensure(&p->dphi, &p->cap_dphi, 3 * p->sum_n))) return st;
   if (precision == RPIM_MIXED && (st = ensure(&p->dphi32, &p->cap_dphi32, 3 * p->sum_n))) return st;
-  if (keep_factors) {
+  if (keep_factors && p->shape_kind == RPIM_SHAPE_RPIM) {
     if ((st = ensure(&p->lu, &p->cap_lu, p->lu_doubles)) || (st = ensure(&p->piv, &p->cap_piv, p->sum_n + 4 * p->G)) ||
         (st = ensure(&p->gam, &p->cap_gam, 3 * (p->sum_n + 4 * p->G))))
       return st;
   }
   if (p->have_factors) ++p->factor_gen;
   p->have_factors = false;
+  if (p->shape_kind != RPIM_SHAPE_RPIM) {  // moving least squares: gradients, then the same gather
+    phase_begin(p, RPIM_PHASE_SHAPE, s);
+    if ((st = launch_mls(p, node_xyz, p->dphi, precision == RPIM_MIXED ? p->dphi32 : nullptr, nullptr, s)) !=
+        RPIM_OK)
+      return st;
+    phase_end(p, RPIM_PHASE_SHAPE, s);
+    phase_begin(p, RPIM_PHASE_GATHER, s);
+    if ((st = launch_rowgather(p, cell_E, nu, precision, K_vals, s)) != RPIM_OK) return st;
+    phase_end(p, RPIM_PHASE_GATHER, s);
+    return RPIM_OK;
+  }
   phase_begin(p, RPIM_PHASE_PAIRS, s);
   if ((st = launch_pair_table(p, node_xyz, s)) != RPIM_OK) return st;
   phase_end(p, RPIM_PHASE_PAIRS, s);
@@ -282,7 +293,7 @@ rpim_status rpim_assemble(rpim_plan* p, const double* node_xyz, const double* ce
 rpim_status rpim_assemble_backward(rpim_plan* p, const double* node_xyz, const double* cell_E, double nu,
                                    const double* dK_vals, double* dE_cell, double* dX_node, void* stream) {
   if (!p || !node_xyz || !cell_E || !dK_vals || !dE_cell || !dX_node) return RPIM_E_ARG;
-  if (!p->built || !p->have_factors) return RPIM_E_STATE;
+  if (!p->built || !p->have_factors || p->shape_kind != RPIM_SHAPE_RPIM) return RPIM_E_STATE;
   if (!(nu > -1.0 && nu < 0.5)) return RPIM_E_ARG;
   return launch_backward(p, node_xyz, cell_E, nu, dK_vals, dE_cell, dX_node, (hipStream_t)stream);
 }
@@ -537,7 +548,9 @@ rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t*
 
 rpim_status rpim_shape_values(rpim_plan* p, const double* node_xyz, double* phi, void* stream) {
   if (!p || !node_xyz || !phi) return RPIM_E_ARG;
-  if (!p->built || !p->have_factors) return RPIM_E_STATE;
+  if (!p->built) return RPIM_E_STATE;
+  if (p->shape_kind != RPIM_SHAPE_RPIM) return launch_mls(p, node_xyz, nullptr, nullptr, phi, (hipStream_t)stream);
+  if (!p->have_factors) return RPIM_E_STATE;
   return launch_shape_values(p, node_xyz, phi, (hipStream_t)stream);
 }
 
@@ -578,6 +591,17 @@ rpim_status rpim_set_solver(rpim_plan* p, int nmax, int kind) {
     return RPIM_E_ARG;
   for (int b = 0; b < kMaxBuckets; ++b)
     if (nmax == 0 || b == (nmax + kBucketStep - 1) / kBucketStep) p->solver_kind[b] = (int8_t)kind;
+  return RPIM_OK;
+}
+
+rpim_status rpim_set_shape_functions(rpim_plan* p, int kind) {
+  if (!p) return RPIM_E_ARG;
+  if (kind != RPIM_SHAPE_RPIM && kind != RPIM_SHAPE_MLS && kind != RPIM_SHAPE_SHEPARD) return RPIM_E_ARG;
+  if (kind != p->shape_kind) {
+    if (p->have_factors) ++p->factor_gen;
+    p->have_factors = false;
+    p->shape_kind = kind;
+  }
   return RPIM_OK;
 }
 

@@ -93,6 +93,7 @@ struct rpim_plan {
   std::vector<rpim::Bucket> buckets;
   // solver kernel per bucket (index nmax / kBucketStep): RPIM_SOLVER_* from rpim.h
   int8_t solver_kind[rpim::kMaxBuckets] = {};
+  int shape_kind = 0;  // RPIM_SHAPE_* from rpim.h
   int32_t* gp_order = nullptr;   // [G] Gauss points grouped by bucket
   // rebuild reuse: capacities of the pattern arrays whose size follows the
   // geometry, and one buffer for the temporaries of a build
@@ -203,6 +204,7 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
 
 // --- post.hip ----------------------------------------------------------------
 rpim_status launch_shape_values(rpim_plan* p, const double* X, double* phi, hipStream_t s);
+rpim_status launch_mls(rpim_plan* p, const double* X, double* dphi, float* dphi32, double* phi, hipStream_t s);
 rpim_status launch_body_force(rpim_plan* p, const double* phi, const double* gp_force, double* f, hipStream_t s);
 rpim_status launch_gauss_stress(rpim_plan* p, const double* E, double nu, const double* u, double* sigma,
                                 hipStream_t s);
