@@ -207,6 +207,11 @@ def host_info():
     return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_available": avail}
 
 
+def software_info():
+    import torch
+    return {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None), "python": sys.version.split()[0]}
+
+
 def cpu_baseline(prob, cell_stride, n_vec=8):
     """Oracle (serial, one core) on the Gauss points of every cell_stride-th cell of the workload,
     spread over the whole domain: support search, pattern, FP64 assembly and adjoint, scaled to Gauss
@@ -377,6 +382,7 @@ def main():
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": shape_traffic(),
                      "flops_per_step": flops, "launches_per_step": info["n_buckets"],
                      "ms_per_step": shape_ms},
+        "software": software_info(),
     }
 
     if not args.no_extras:
@@ -415,6 +421,27 @@ def main():
         out["hbm_gbps_fp64_assembly"] = alg_bytes / t_fp64 / 1e9
         log(f"assemble fp64 {t_fp64 * 1e3:.2f} ms, mixed {t_mixed * 1e3:.2f} ms (err {err32:.2e}), "
             f"bwd {t_bwd * 1e3:.2f} ms, bwd/fwd {out['bwd_fwd']:.2f}")
+        # the same slope with moving-least-squares and Shepard shape functions (same supports, same
+        # gather); the gradient kernel's algorithmic bytes: per support entry the node id, its
+        # coordinates and the gradient written, per point its support range and coordinates
+        shapes = {}
+        mls_bytes = sum_n * (4 + 24 + 24) + prob.n_gp * (16 + 24)
+        plan.profile(True)
+        for kind in ("mls", "shepard"):
+            plan.set_shape_functions(kind)
+            t64 = timed(lambda: plan.assemble(X, E, prob.nu, rp.FP64, out=Kout))
+            kshape = plan.profile_read()["shape"]
+            t32 = timed(lambda: plan.assemble(X, E, prob.nu, rp.MIXED, out=K32))
+            shapes[kind] = {"assemble_ms": {"fp64": t64 * 1e3, "mixed": t32 * 1e3},
+                            "assemble_gp_per_s": {"fp64": prob.n_gp / t64, "mixed": prob.n_gp / t32},
+                            "gradient_kernel_ms": kshape,
+                            "gradient_kernel_gbps": mls_bytes / (kshape * 1e-3) / 1e9,
+                            "mixed_rel_fro_err": float(torch.linalg.norm(K32.double() - Kout.double()) /
+                                                       torch.linalg.norm(Kout))}
+            log(f"{kind}: assemble fp64 {t64 * 1e3:.2f} ms, gradients {kshape:.3f} ms")
+        plan.profile(False)
+        plan.set_shape_functions("rpim")
+        out["shape_functions"] = shapes
 
     if not args.no_extras and not args.no_batched:
         out["batched"] = batched_leg()

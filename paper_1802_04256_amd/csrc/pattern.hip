@@ -43,12 +43,15 @@ __global__ void __launch_bounds__(256) k_bbox(const double* X, const int64_t* no
   const int m = blockIdx.x;
   const int64_t b = node_off[m], e = node_off[m + 1];
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;  // a non-finite coordinate makes the box NaN, which the host rejects
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x)
     for (int k = 0; k < 3; ++k) {
       double v = X[3 * i + k];
+      bad |= !isfinite(v);
       lo[k] = fmin(lo[k], v);
       hi[k] = fmax(hi[k], v);
     }
+  bad = __syncthreads_or(bad);
   __shared__ double red[6][256];
   for (int k = 0; k < 3; ++k) { red[k][threadIdx.x] = lo[k]; red[3 + k][threadIdx.x] = hi[k]; }
   __syncthreads();
@@ -60,15 +63,21 @@ __global__ void __launch_bounds__(256) k_bbox(const double* X, const int64_t* no
       }
     __syncthreads();
   }
-  if (threadIdx.x < 6) out[6 * m + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 6) out[6 * m + threadIdx.x] = bad ? NAN : red[threadIdx.x][0];
+}
+
+// Bin of a point, clamped to the grid in floating point before the integer
+// conversion (a point outside the grid, or NaN, lands in a valid bin and then
+// simply finds no node within the radius).
+__device__ __forceinline__ int bin_index(double f, int n) {
+  return f >= 0.0 ? (f < (double)n ? (int)f : n - 1) : 0;
 }
 
 __device__ __forceinline__ void bin_coords(const BinGrid& gr, double x, double y, double z, int* ix, int* iy,
                                            int* iz) {
-  int a = (int)floor((x - gr.ox) / gr.h), b = (int)floor((y - gr.oy) / gr.h), c = (int)floor((z - gr.oz) / gr.h);
-  *ix = min(max(a, 0), gr.nx - 1);
-  *iy = min(max(b, 0), gr.ny - 1);
-  *iz = min(max(c, 0), gr.nz - 1);
+  *ix = bin_index(floor((x - gr.ox) / gr.h), gr.nx);
+  *iy = bin_index(floor((y - gr.oy) / gr.h), gr.ny);
+  *iz = bin_index(floor((z - gr.oz) / gr.h), gr.nz);
 }
 
 // ---- 1. binning -------------------------------------------------------------

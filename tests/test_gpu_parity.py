@@ -316,3 +316,22 @@ def test_rebuild_pattern_equals_fresh_plan():
         b = fresh.assemble_backward(X, E, prob.nu, dK)
         for u, v in zip(a, b):
             assert torch.equal(u, v)
+
+
+def test_nan_coordinates_reported():
+    # a NaN node coordinate is rejected before any search (bounding box);
+    # a NaN Gauss point finds no support node and is reported as that point
+    import paper_1802_04256_amd as rp
+    prob = W.cantilever()
+    prob.node_xyz[7, 1] = np.nan
+    plan = rp.Plan.from_problem(prob)
+    with pytest.raises(rp.RpimError) as ei:
+        plan.build_pattern()
+    assert ei.value.code == -1
+    prob = W.cantilever()
+    prob.gp_xyz[11, 2] = np.nan
+    plan = rp.Plan.from_problem(prob)
+    with pytest.raises(rp.RpimError) as ei:
+        plan.build_pattern()
+    assert ei.value.code == -4
+    assert "first bad gauss point 11" in str(ei.value)
