@@ -42,6 +42,15 @@ SMALL = {
 }
 
 
+_ORACLE_K = {}  # (case, precision) -> the oracle's K: several tests compare against the same one
+
+
+def oracle_K(name, m, precision=0):
+    if (name, precision) not in _ORACLE_K:
+        _ORACLE_K[(name, precision)] = m.assemble(precision=precision)
+    return _ORACLE_K[(name, precision)].copy()
+
+
 @pytest.fixture(scope="module", params=list(SMALL))
 def case(request, oracle_mod, rp):
     prob = SMALL[request.param]()
@@ -86,7 +95,7 @@ def test_K_fp64_bitwise(case):
     name, prob, m, plan = case
     K = plan.assemble(cell_E=prob.cell_E, nu=prob.nu).cpu().numpy()
     plan.status()
-    Ko = m.assemble()
+    Ko = oracle_K(name, m)
     err = rel_fro(K, Ko)
     print(f"[{name}] FP64 K rel Frobenius error {err:.3e}")
     assert err <= 1e-12
@@ -97,8 +106,8 @@ def test_K_mixed(case):
     name, prob, m, plan = case
     K32 = plan.assemble(cell_E=prob.cell_E, nu=prob.nu, precision="mixed").cpu().numpy()
     plan.status()
-    Ko32 = m.assemble(precision=1)
-    Ko64 = m.assemble()
+    Ko32 = oracle_K(name, m, 1)
+    Ko64 = oracle_K(name, m)
     assert K32.dtype == np.float32
     assert np.array_equal(K32, Ko32)
     err = rel_fro(K32, Ko64)
@@ -123,7 +132,7 @@ def test_penalty_matches_oracle(case, oracle_mod):
     ub = np.linspace(-1e-3, 1e-3, len(fixed))
     rhs = torch.zeros(3 * prob.n_nodes, dtype=torch.float64, device="cuda")
     alpha = rp_apply(plan, K, fixed, ub, rhs)
-    Ko = m.assemble()
+    Ko = oracle_K(name, m)
     rhs_o = np.zeros(3 * prob.n_nodes)
     rp_o, ci_o = m.pattern()
     alpha_o = oracle_mod.penalty(rp_o, ci_o, Ko, fixed, u_bar=ub, factor=1e8, rhs=rhs_o)
