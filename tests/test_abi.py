@@ -74,3 +74,23 @@ def test_package_has_no_cpu_fallback():
     import paper_1802_04256_amd as rp
     src = open(os.path.join(os.path.dirname(rp.__file__), "__init__.py")).read()
     assert "import oracle" not in src and "from oracle" not in src
+
+
+def test_backward_refuses_factors_of_another_forward():
+    # the autograd backward reuses the factors its forward kept; once a later
+    # forward (or a rebuild, or autotune) has replaced them it must refuse
+    import paper_1802_04256_amd as rp
+
+    class Plan:
+        def __init__(self, gen):
+            self.gen = gen
+
+        def factor_generation(self):
+            return self.gen
+
+    rp._check_factors(Plan(3), 3)
+    with pytest.raises(rp.RpimError) as ei:
+        rp._check_factors(Plan(4), 3)
+    assert ei.value.code == -8
+    with pytest.raises(rp.RpimError):
+        rp._check_factors(Plan(3), 0)  # the forward kept nothing

@@ -149,3 +149,21 @@ def test_backward_large_supports(oracle_mod):
     dEo, dXo = m.backward(Kb)
     assert rel_err(dE.cpu().numpy(), dEo) < 1e-10
     assert rel_err(dX.cpu().numpy(), dXo) < 1e-6
+
+
+def test_backward_of_an_older_forward_raises():
+    import torch
+    import paper_1802_04256_amd as rp
+    prob = W.cantilever()
+    plan = rp.Plan.from_problem(prob)
+    plan.build_pattern()
+    E = torch.from_numpy(prob.cell_E.copy()).cuda()
+    X1 = torch.from_numpy(prob.node_xyz.copy()).cuda().requires_grad_(True)
+    X2 = torch.from_numpy(prob.node_xyz * 1.001).cuda().requires_grad_(True)
+    K1 = rp.assemble(plan, X1, E, prob.nu)
+    K2 = rp.assemble(plan, X2, E, prob.nu)
+    with pytest.raises(rp.RpimError) as ei:
+        K1.sum().backward()
+    assert ei.value.code == -8
+    K2.sum().backward()  # the latest forward still differentiates
+    assert X2.grad is not None and torch.isfinite(X2.grad).all()
