@@ -259,10 +259,35 @@ __global__ void __launch_bounds__(256) k_blocks_union(const int64_t* inv_ptr, co
   for (int i = threadIdx.x; i < nw; i += blockDim.x) bm[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t e = inv_ptr[I] + w; e < inv_ptr[I + 1]; e += 4) {
+  // each wave takes every fourth point of I's list; the next point's support
+  // range is loaded while this point's ids are read and entered
+  const int64_t e1 = inv_ptr[I + 1];
+  int64_t e = inv_ptr[I] + w;
+  int64_t bn = 0, nn = 0;
+  if (e < e1) {
     const int64_t g = (int64_t)(inv_key[e] >> 8);
-    const int64_t b = gp_ptr[g], n = gp_ptr[g + 1] - b;
-    for (int64_t a = lane; a < n; a += 64) {
+    bn = gp_ptr[g];
+    nn = gp_ptr[g + 1] - bn;
+  }
+  for (; e < e1; e += 4) {
+    const int64_t b = bn, n = nn;
+    int32_t id0 = 0, id1 = 0;
+    if (lane < n) id0 = gp_nbr[b + lane];
+    if (lane + 64 < n) id1 = gp_nbr[b + lane + 64];
+    if (e + 4 < e1) {
+      const int64_t g = (int64_t)(inv_key[e + 4] >> 8);
+      bn = gp_ptr[g];
+      nn = gp_ptr[g + 1] - bn;
+    }
+    if (lane < n) {
+      const int r = id0 - lo;
+      atomicOr(&bm[r >> 5], 1u << (r & 31));
+    }
+    if (lane + 64 < n) {
+      const int r = id1 - lo;
+      atomicOr(&bm[r >> 5], 1u << (r & 31));
+    }
+    for (int64_t a = lane + 128; a < n; a += 64) {  // supports above 128 nodes
       const int r = gp_nbr[b + a] - lo;
       atomicOr(&bm[r >> 5], 1u << (r & 31));
     }
@@ -346,17 +371,34 @@ __global__ void k_expand_cols(int64_t nblk, const int64_t* blk_ptr, const int32_
 // Bucket of each Gauss point (N = n + 4 rounded up to kBucketStep), its packed
 // factor size N^2, the bucket sizes and the smallest and largest support
 // (integer atomics: the totals do not depend on the order).
-__global__ void k_point_sizes(int64_t G, const int64_t* gp_ptr, int32_t* bkt, int64_t* nsq,
-                              unsigned long long* bcount, int* nrange) {
+// Counted in LDS per block first, then one global atomic per bucket and block.
+__global__ void __launch_bounds__(256) k_point_sizes(int64_t G, const int64_t* gp_ptr, int32_t* bkt, int64_t* nsq,
+                                                     unsigned long long* bcount, int* nrange) {
+  __shared__ unsigned c[kMaxBuckets];
+  __shared__ int lo, hi;
+  for (int i = threadIdx.x; i < kMaxBuckets; i += blockDim.x) c[i] = 0;
+  if (threadIdx.x == 0) {
+    lo = INT_MAX;
+    hi = 0;
+  }
+  __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  const int n = (int)(gp_ptr[g + 1] - gp_ptr[g]);
-  const int b = (n + 4 + kBucketStep - 1) / kBucketStep;
-  bkt[g] = b;
-  nsq[g] = (int64_t)(n + 4) * (n + 4);
-  atomicAdd(&bcount[b], 1ull);
-  atomicMin(&nrange[0], n);
-  atomicMax(&nrange[1], n);
+  if (g < G) {
+    const int n = (int)(gp_ptr[g + 1] - gp_ptr[g]);
+    const int b = (n + 4 + kBucketStep - 1) / kBucketStep;
+    bkt[g] = b;
+    nsq[g] = (int64_t)(n + 4) * (n + 4);
+    atomicAdd(&c[b], 1u);
+    atomicMin(&lo, n);
+    atomicMax(&hi, n);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kMaxBuckets; i += blockDim.x)
+    if (c[i]) atomicAdd(&bcount[i], (unsigned long long)c[i]);
+  if (threadIdx.x == 0 && hi > 0) {
+    atomicMin(&nrange[0], lo);
+    atomicMax(&nrange[1], hi);
+  }
 }
 
 constexpr int kOrderTile = 1024;  // Gauss points per tile of the bucket grouping
