@@ -193,17 +193,20 @@ __global__ void k_inv_fill(int64_t G, const int64_t* gp_ptr, const int32_t* gp_n
   }
 }
 
-// Bitonic sort of each node's inverse list in LDS (P = power of two >= longest).
+// Bitonic sort of each node's inverse list in LDS, at the list's own power of
+// two (the LDS holds P >= the longest list).
 __global__ void __launch_bounds__(1024) k_inv_sort(const int64_t* inv_ptr, uint64_t* inv_key, int P) {
   extern __shared__ uint64_t keys[];
   const int64_t I = blockIdx.x;
   const int64_t b = inv_ptr[I];
   const int n = (int)(inv_ptr[I + 1] - b);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = i < n ? inv_key[b + i] : ~0ull;
+  int Q = 2;
+  while (Q < n) Q <<= 1;  // <= P
+  for (int i = threadIdx.x; i < Q; i += blockDim.x) keys[i] = i < n ? inv_key[b + i] : ~0ull;
   __syncthreads();
-  for (int k = 2; k <= P; k <<= 1)
+  for (int k = 2; k <= Q; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+      for (int i = threadIdx.x; i < Q; i += blockDim.x) {
         const int l = i ^ j;
         if (l > i) {
           const uint64_t x = keys[i], y = keys[l];
