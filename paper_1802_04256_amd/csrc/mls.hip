@@ -91,7 +91,8 @@ __global__ void __launch_bounds__(64) k_mls(int64_t G, const int64_t* gp_ptr, co
           l = ll;
         }
     double s = 0.0;
-    for (int a = 0; a < n; ++a) {
+#pragma unroll 8
+    for (int a = 0; a < n; ++a) {  // the loads run ahead, the sum stays in order
       const double wa = c == 0 ? Wv[a] : wk[c - 1][a];
       const double pj = j == 0 ? 1.0 : qv[j - 1][a];
       const double pl = l == 0 ? 1.0 : qv[l - 1][a];
