@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/shape_panel.hip",
                  "paper_1802_04256_amd/csrc/shape_common.h", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "f38ea0490bade17caa386d69101722ba507a88ac8b4605db0c34497dcc9d24a0", "bytes_per_step": 3.4495e10}
+SHAPE_TRAFFIC = {"sources_sha256": "273ae03d186c4db92b8c9fa7360d9d61f084a6f2f32d1a072a5263f34262f771", "bytes_per_step": 3.4492e10}
 
 
 def log(*a):
