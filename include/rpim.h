@@ -242,8 +242,8 @@ rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t*
  * For every support-size bucket it times the moment-matrix solver kernels
  * that can hold the bucket (RPIM_SOLVER_WINDOW, RPIM_SOLVER_PANEL; the LDS
  * kernel beyond them) and keeps the fastest for the bucket; then it times the
- * row gather of `precision` with 2, 3 and 4 waves per node row and keeps the
- * fastest.  Every configuration computes the same bits; only speed differs.
+ * row gather of `precision` with 1, 2, 3 and 4 waves per node row and keeps
+ * the fastest.  Every configuration computes the same bits; only speed differs.
  * K_vals (nnz values of the precision's type) serves as scratch and is
  * overwritten.  The choices go to a process-wide cache keyed by (GPU
  * architecture, precision, bucket size) and (architecture, precision); when
@@ -252,8 +252,8 @@ rpim_status rpim_apply_penalty_bc_noalloc(const int64_t* row_ptr, const int32_t*
  * must be built (RPIM_E_STATE otherwise). */
 #define RPIM_TUNING_MAX_BUCKETS 32
 typedef struct {
-  int32_t gather_waves;                          /* chosen: 2, 3 or 4              */
-  float gather_ms[3];                            /* row gather with 2, 3, 4 waves  */
+  int32_t gather_waves;                          /* chosen: 1, 2, 3 or 4           */
+  float gather_ms[4];                            /* row gather with 1 to 4 waves   */
   int32_t n_buckets;                             /* buckets reported (<= 32)       */
   int32_t bucket_nmax[RPIM_TUNING_MAX_BUCKETS];  /* padded size N of each bucket   */
   int64_t bucket_points[RPIM_TUNING_MAX_BUCKETS];
@@ -271,7 +271,7 @@ rpim_status rpim_autotune(rpim_plan* plan, const double* node_xyz, const double*
 rpim_status rpim_tuning_cache_save(const char* path);
 rpim_status rpim_tuning_cache_load(const char* path);
 void rpim_tuning_cache_clear(void);
-/* Set the row-gather configuration (2, 3 or 4 waves per node row) for
+/* Set the row-gather configuration (1, 2, 3 or 4 waves per node row) for
  * `precision` by hand, as rpim_autotune would; RPIM_E_ARG otherwise. */
 rpim_status rpim_set_gather_waves(rpim_plan* plan, int precision, int waves);
 

@@ -43,7 +43,7 @@ _TUNING_MAX = 32
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("gather_waves", C.c_int32), ("gather_ms", C.c_float * 3), ("n_buckets", C.c_int32),
+    _fields_ = [("gather_waves", C.c_int32), ("gather_ms", C.c_float * 4), ("n_buckets", C.c_int32),
                 ("bucket_nmax", C.c_int32 * _TUNING_MAX), ("bucket_points", C.c_int64 * _TUNING_MAX),
                 ("bucket_ms", C.c_float * _TUNING_MAX), ("bucket_solver", C.c_int32 * _TUNING_MAX),
                 ("bucket_ms_window", C.c_float * _TUNING_MAX), ("bucket_ms_panel", C.c_float * _TUNING_MAX),
@@ -257,7 +257,7 @@ class Plan:
         n = t.n_buckets
         kinds = {v: k for k, v in self.SOLVERS.items()}
         return {"gather_waves": t.gather_waves, "from_cache": bool(t.from_cache),
-                "gather_ms": {w: t.gather_ms[w - 2] for w in (2, 3, 4)},
+                "gather_ms": {w: t.gather_ms[w - 1] for w in (1, 2, 3, 4)},
                 "buckets": [{"nmax": t.bucket_nmax[i], "points": t.bucket_points[i], "ms": t.bucket_ms[i],
                              "solver": kinds.get(t.bucket_solver[i], t.bucket_solver[i]),
                              "ms_window": t.bucket_ms_window[i], "ms_panel": t.bucket_ms_panel[i]}

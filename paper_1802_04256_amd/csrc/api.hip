@@ -373,7 +373,7 @@ rpim_status rpim_autotune(rpim_plan* p, const double* node_xyz, const double* ce
       }
       t.n_buckets = nb;
       t.gather_waves = gw;
-      t.gather_ms[0] = t.gather_ms[1] = t.gather_ms[2] = -1.f;
+      t.gather_ms[0] = t.gather_ms[1] = t.gather_ms[2] = t.gather_ms[3] = -1.f;
       t.from_cache = 1;
       if (out) *out = t;
       return RPIM_OK;
@@ -448,8 +448,8 @@ rpim_status rpim_autotune(rpim_plan* p, const double* node_xyz, const double* ce
   // the gradients with the chosen kernels (every kernel gives the same bits)
   if (st == RPIM_OK) st = launch_shape(p, node_xyz, 0, d32, s);
   int best = 0;
-  for (int i = 0; i < 3 && st == RPIM_OK; ++i) {
-    const int gw = 2 + i;
+  for (int i = 0; i < 4 && st == RPIM_OK; ++i) {
+    const int gw = 1 + i;
     float ms = 0.f, best_ms = 0.f;
     for (int rep = 0; rep < 3 && st == RPIM_OK; ++rep) {  // first run warms caches and sets LDS limits
       st = timed([&] { return launch_rowgather(p, cell_E, nu, precision, K_vals, s, gw); }, &ms);
@@ -461,7 +461,7 @@ rpim_status rpim_autotune(rpim_plan* p, const double* node_xyz, const double* ce
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != RPIM_OK) return st;
-  t.gather_waves = 2 + best;
+  t.gather_waves = 1 + best;
   p->gather_waves[precision == RPIM_MIXED ? 1 : 0] = t.gather_waves;
   cache_put(tune_key(arch, precision, "gather", 0), t.gather_waves);
   if (out) *out = t;

@@ -221,9 +221,12 @@ __global__ void __launch_bounds__(kThreads) k_shape(const int32_t* gp_order, int
 // slots of its range, so no slot is touched by two waves.  Each wave walks the
 // row's Gauss points in ascending g; since supports are sorted, the part of a
 // point's support inside the wave's range is a contiguous run, found with two
-// ballots, and its entries go one per lane, each lane adding all nine entries
-// of its 3x3 block.  A wave's LDS accesses execute in program order, so every
-// slot receives its contributions in ascending g without barriers.
+// ballots (with GW = 1 it is the support from I's own entry on), and its
+// entries go one per lane, each lane adding all nine entries of its 3x3 block.
+// A wave's LDS accesses execute in program order, so every slot receives its
+// contributions in ascending g without barriers.  GW = 1 reads each point's
+// metadata once per row instead of once per wave; more waves per row shorten
+// the row's serial walk when rows are few.
 template <bool kMixed, int GW>
 __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, const int32_t* blk_col,
                                                               const int32_t* row_lo,
@@ -295,6 +298,10 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   };
   auto split = [&](const Meta& m) {
     Split sp;
+    if constexpr (GW == 1) {  // one wave owns every upper column: no run to locate
+      sp.J0 = sp.J1 = 0;
+      return sp;
+    }
     const int b1 = lane + 64 < m.n ? lane + 64 : m.n - 1;
     sp.J0 = gp_nbr[m.b0 + (lane < m.n ? lane : m.n - 1)];
     sp.J1 = gp_nbr[m.b0 + b1];
@@ -303,9 +310,14 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   auto run = [&](const Meta& m, const Split& sp) {
     Run r;
     // supports are sorted: the count of ids below a threshold is a position
-    const bool v0 = lane < m.n, v1 = lane + 64 < m.n;
-    r.lo = __popcll(__ballot(v0 && sp.J0 < thr_lo)) + __popcll(__ballot(v1 && sp.J1 < thr_lo));
-    r.hi = __popcll(__ballot(v0 && sp.J0 < thr_hi)) + __popcll(__ballot(v1 && sp.J1 < thr_hi));
+    if constexpr (GW == 1) {  // the upper part starts at I's own entry
+      r.lo = m.aI;
+      r.hi = m.n;
+    } else {
+      const bool v0 = lane < m.n, v1 = lane + 64 < m.n;
+      r.lo = __popcll(__ballot(v0 && sp.J0 < thr_lo)) + __popcll(__ballot(v1 && sp.J1 < thr_lo));
+      r.hi = __popcll(__ballot(v0 && sp.J0 < thr_hi)) + __popcll(__ballot(v1 && sp.J1 < thr_hi));
+    }
     const int b = r.lo + lane;
     const int bc = b < m.n ? b : m.n - 1;
     r.J = gp_nbr[m.b0 + bc];
@@ -482,7 +494,7 @@ rpim_status launch_gather_t(rpim_plan* p, const double* E, double lam, double mu
   return RPIM_OK;
 }
 
-int gather_waves_valid(int gw) { return gw == 2 || gw == 3 || gw == 4; }
+int gather_waves_valid(int gw) { return gw >= 1 && gw <= 4; }
 
 rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s,
                              int gather_waves) {
@@ -496,15 +508,17 @@ rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int preci
   const int gw = gather_waves > 0 ? gather_waves : p->gather_waves[precision == RPIM_MIXED ? 1 : 0];
   if (precision == RPIM_FP64) {
     switch (gw) {
+      case 2: return launch_gather_t<false, 2>(p, E, lam, mu, K, lds, s);
       case 3: return launch_gather_t<false, 3>(p, E, lam, mu, K, lds, s);
       case 4: return launch_gather_t<false, 4>(p, E, lam, mu, K, lds, s);
-      default: return launch_gather_t<false, 2>(p, E, lam, mu, K, lds, s);
+      default: return launch_gather_t<false, 1>(p, E, lam, mu, K, lds, s);
     }
   }
   switch (gw) {
+    case 2: return launch_gather_t<true, 2>(p, E, lam, mu, K, lds, s);
     case 3: return launch_gather_t<true, 3>(p, E, lam, mu, K, lds, s);
     case 4: return launch_gather_t<true, 4>(p, E, lam, mu, K, lds, s);
-    default: return launch_gather_t<true, 2>(p, E, lam, mu, K, lds, s);
+    default: return launch_gather_t<true, 1>(p, E, lam, mu, K, lds, s);
   }
 }
 

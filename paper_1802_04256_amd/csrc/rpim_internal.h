@@ -131,7 +131,7 @@ struct rpim_plan {
   rpim::DevStatus* status = nullptr;
 
   // launch configurations chosen by rpim_autotune (defaults until then)
-  int gather_waves[2] = {2, 2};  // row-gather waves per node row: [FP64, mixed]
+  int gather_waves[2] = {1, 1};  // row-gather waves per node row: [FP64, mixed]
 
   // capacities (elements) of the workspaces above, so a rebuilt pattern can reuse them
   int64_t cap_R = 0, cap_dphi = 0, cap_dphi32 = 0, cap_lu = 0, cap_piv = 0, cap_gam = 0;
@@ -186,7 +186,7 @@ rpim_status launch_pair_table(rpim_plan* p, const double* X, hipStream_t s);
 rpim_status launch_shape(rpim_plan* p, const double* X, int keep, float* dphi32, hipStream_t s);
 rpim_status launch_shape_bucket(rpim_plan* p, const Bucket& b, const double* X, int keep, float* dphi32,
                                 hipStream_t s);
-// gather_waves: waves per row of the gather (2, 3 or 4), 0 = the plan's tuned choice
+// gather_waves: waves per row of the gather (1 to 4), 0 = the plan's tuned choice
 rpim_status launch_rowgather(rpim_plan* p, const double* E, double nu, int precision, void* K, hipStream_t s,
                              int gather_waves = 0);
 int gather_waves_valid(int gw);

@@ -19,15 +19,17 @@ def test_gather_configurations_agree_and_autotune(precision):
     plan.build_pattern()
     E = torch.from_numpy(prob.cell_E).cuda()
     ref = plan.assemble(cell_E=E, nu=prob.nu, precision=precision).cpu().numpy()
-    for waves in (2, 3, 4):
+    for waves in (1, 2, 3, 4):
         plan.set_gather_waves(precision, waves)
         K = plan.assemble(cell_E=E, nu=prob.nu, precision=precision).cpu().numpy()
         assert np.array_equal(K, ref), waves
     with pytest.raises(rp.RpimError):
         plan.set_gather_waves(precision, 5)
+    with pytest.raises(rp.RpimError):
+        plan.set_gather_waves(precision, 0)
     t = plan.autotune(cell_E=E, nu=prob.nu, precision=precision)
     print(t)
-    assert t["gather_waves"] in (2, 3, 4)
+    assert t["gather_waves"] in (1, 2, 3, 4)
     assert all(v > 0 for v in t["gather_ms"].values())
     info = plan.info()
     assert len(t["buckets"]) == info["n_buckets"]
