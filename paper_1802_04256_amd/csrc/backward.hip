@@ -149,8 +149,11 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
 // for the back substitution (right-hand sides in registers); each step's
 // factor entry is loaded before the step's barrier.  The chain rule runs over
 // (a, b) pairs with four threads per support node a and a fixed-order
-// shuffle reduction of their partial sums.
-__global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr,
+// shuffle reduction of their partial sums.  The kernel is bound by the
+// latency of its dependent chains (substitution steps, the pair-table
+// gathers), so it is held to five waves per SIMD: faster, measured, than four
+// waves without the few registers' worth of spills that five cost.
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5))) k_bwd_gp(const int32_t* gp_order, int64_t order_begin, const int64_t* gp_ptr,
                                                const int32_t* gp_nbr, const int64_t* blk_ptr,
                                                const int32_t* row_lo, const int64_t* rbm_off, const uint2* rbm,
                                                const double* R, const double* X,
@@ -169,7 +172,8 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   double* gm = lamv + 3 * N;      // [3][N] gamma_k
   double* y = gm + 3 * N;         // [3][N] forward values by position
   double* xs = y + 3 * N;         // [n][3] support coordinates
-  int64_t* rwbS = (int64_t*)(xs + 3 * n);  // [n] rank-word offset of each support node's row
+  double* tq = xs + 3 * n;        // [2][n] R/t and R/t^2 of the RPIM basis at the point, per support node
+  int64_t* rwbS = (int64_t*)(tq + 2 * n);  // [n] rank-word offset of each support node's row
   int64_t* rbpS = rwbS + n;                // [n] pattern start of each support node's row
   int* S = (int*)(rbpS + n);      // [n]
   int* ppos = S + n;              // [N] position of each step's pivot before its interchange
@@ -195,6 +199,17 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
   if (own && tid < n)
     for (int k = 0; k < 3; ++k) b[k] = pbar[3 * (b0 + tid) + k];
   __syncthreads();
+  // the basis R(x_g, x_a) = t^q and its two quotients, one lane per support
+  // node (kept apart from the chain rule's live values); the solve's barriers
+  // order these LDS writes before their use
+  for (int a = tid; a < n; a += nT) {
+    const double dgx[3] = {xg[0] - xs[3 * a], xg[1] - xs[3 * a + 1], xg[2] - xs[3 * a + 2]};
+    const double t = __builtin_fma(-dgx[2], -dgx[2], __builtin_fma(-dgx[1], -dgx[1], dgx[0] * dgx[0])) + C2;
+    bool hard = false;
+    const double Rg = pow_cr(t, q, &hard);
+    tq[a] = Rg / t;
+    tq[n + a] = Rg / (t * t);
+  }
   // lambda_k = G^-1 [Phibar_k; 0] with the kept factors (G symmetric)
   kept_solve<3>(Fm, ppos, N, tid, b, y, lamv);
   // chain rule: four threads per support node a, partial sums over b = sub mod 4
@@ -256,10 +271,7 @@ __global__ void __launch_bounds__(kT) k_bwd_gp(const int32_t* gp_order, int64_t 
                   lamv[N + i] * ga[1] + lamv[2 * N + i] * ga[2];
       }
       const double dgx[3] = {xg[0] - xa[0], xg[1] - xa[1], xg[2] - xa[2]};
-      const double t = __builtin_fma(-dgx[2], -dgx[2], __builtin_fma(-dgx[1], -dgx[1], dgx[0] * dgx[0])) + C2;
-      bool hard = false;
-      const double Rg = pow_cr(t, q, &hard);
-      const double tq1 = Rg / t, tq2 = Rg / (t * t);
+      const double tq1 = tq[a], tq2 = tq[n + a];
       for (int cc = 0; cc < 3; ++cc) {
         double s2 = 0.0;
         for (int k = 0; k < 3; ++k) {
@@ -356,7 +368,7 @@ rpim_status launch_backward(rpim_plan* p, const double* X, const double* E, doub
   phase_begin(p, RPIM_PHASE_BWD_GP, s);
   for (const Bucket& b : p->buckets) {
     const int N = b.nmax;
-    const size_t lds = sizeof(double) * 12 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(3 * N);
+    const size_t lds = sizeof(double) * 14 * (size_t)N + sizeof(int64_t) * 2 * (size_t)N + sizeof(int) * (size_t)(3 * N);
     const int threads = 64 * ((N + 63) / 64);  // whole waves, at least one thread per unknown
     if (threads > kT) return RPIM_E_RANGE;
     hipLaunchKernelGGL(k_bwd_gp, dim3((unsigned)b.count), dim3(threads), lds, s, (const int32_t*)p->gp_order, b.begin,
