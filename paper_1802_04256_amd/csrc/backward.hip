@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
       const int n = (int)(gp_ptr[g + 1] - b0);
       const double w = wdet[g];
       const double c = w * E[gp_cell[g]];
-      const double lc = c * lam, mc = c * mu;
+      const double lc = c * lam, mc = c * mu, hw = 0.5 * w;
       const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
 #pragma unroll 2
       for (int b = ql; b < n; b += 16) {
@@ -117,19 +117,21 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
         const double* Mb = Mrow + 9 * pos;
         const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
         const double tr = Mb[0] + Mb[4] + Mb[8];
+        // <M_IJ, k_IJ> with k_IJ = lam pI pb^T + mu pb pI^T + mu (pI . pb) 1 is
+        // lam pI.(M pb) + mu pI.(M^T pb) + mu tr(M) (pI . pb): the products s1 = M pb
+        // and s2 = M^T pb serve both sums
+        // (fused multiply-adds throughout: these sums carry no rounding contract)
+        const double mtr = mc * tr;
+        double d1 = 0.0, d2 = 0.0;
         for (int ga = 0; ga < 3; ++ga) {
-          const double s1 = Mb[3 * ga] * pb[0] + Mb[3 * ga + 1] * pb[1] + Mb[3 * ga + 2] * pb[2];
-          const double s2 = Mb[ga] * pb[0] + Mb[3 + ga] * pb[1] + Mb[6 + ga] * pb[2];
-          v[ga] += lc * s1 + mc * s2 + mc * tr * pb[ga];
+          const double s1 = __builtin_fma(Mb[3 * ga + 2], pb[2], __builtin_fma(Mb[3 * ga + 1], pb[1], Mb[3 * ga] * pb[0]));
+          const double s2 = __builtin_fma(Mb[6 + ga], pb[2], __builtin_fma(Mb[3 + ga], pb[1], Mb[ga] * pb[0]));
+          v[ga] = __builtin_fma(lc, s1, __builtin_fma(mc, s2, __builtin_fma(mtr, pb[ga], v[ga])));
+          d1 = __builtin_fma(pI[ga], s1, d1);
+          d2 = __builtin_fma(pI[ga], s2, d2);
         }
-        const double dot = pI[0] * pb[0] + pI[1] * pb[1] + pI[2] * pb[2];
-        double kk = 0.0;
-        for (int al = 0; al < 3; ++al)
-          for (int be = 0; be < 3; ++be) {
-            const double kv = lam * pI[al] * pb[be] + mu * pI[be] * pb[al] + (al == be ? mu * dot : 0.0);
-            kk += Mb[3 * al + be] * kv;
-          }
-        v[3] += 0.5 * w * kk;
+        const double dot = __builtin_fma(pI[2], pb[2], __builtin_fma(pI[1], pb[1], pI[0] * pb[0]));
+        v[3] = __builtin_fma(hw, __builtin_fma(lam, d1, __builtin_fma(mu, d2, (mu * tr) * dot)), v[3]);
       }
     }
 #pragma unroll
@@ -243,15 +245,19 @@ __global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(5))) k_
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int bb = bb0 + 4 * j;
-          if (bb < n && bb != a) {
-            const double gsum = -(la[0] * gm[bb] + la[1] * gm[N + bb] + la[2] * gm[2 * N + bb] + lamv[bb] * ga[0] +
-                                  lamv[N + bb] * ga[1] + lamv[2 * N + bb] * ga[2]);
+          if (bb < n && bb != a) {  // (fused multiply-adds: no rounding contract here)
+            const double gsum = -__builtin_fma(
+                lamv[2 * N + bb], ga[2],
+                __builtin_fma(lamv[N + bb], ga[1],
+                              __builtin_fma(lamv[bb], ga[0],
+                                            __builtin_fma(la[2], gm[2 * N + bb],
+                                                          __builtin_fma(la[1], gm[N + bb], la[0] * gm[bb])))));
             const double dx = xa[0] - xs[3 * bb], dy = xa[1] - xs[3 * bb + 1], dz = xa[2] - xs[3 * bb + 2];
             const double t = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)) + C2;
             const double f = gsum * (q * Rv[j] / t) * 2.0;
-            acc[0] += f * dx;
-            acc[1] += f * dy;
-            acc[2] += f * dz;
+            acc[0] = __builtin_fma(f, dx, acc[0]);
+            acc[1] = __builtin_fma(f, dy, acc[1]);
+            acc[2] = __builtin_fma(f, dz, acc[2]);
           }
         }
       }
