@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
   const int32_t thr_hi = w + 1 == GW ? INT_MAX : blk_col[rb + pd + (int64_t)(w + 1) * Lu / GW];
   __syncthreads();
 
-  // Software pipeline over the row's Gauss points: point metadata (scalar)
-  // three points ahead, the support ids that locate the wave's run two points
+  // Several waves per row (GW > 1): a software pipeline over the row's Gauss
+  // points, point metadata (scalar) three points ahead, the support ids that locate the wave's run two points
   // ahead, the run's entries one point ahead.  Loads past the row's last point
   // re-read the last point, loads past a support's end re-read its last entry
   // (no branch around a load).
@@ -380,35 +380,115 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
         }
     }
   };
-  const int64_t e_last = e_end - 1;
-  auto clampe = [&](int64_t e) { return e < e_last ? e : e_last; };
-  Meta m_cur = {}, m_nxt = {}, m_n2 = {};
-  Split s_nxt = {}, s_n2 = {};
-  Run r_cur = {};
-  if (e_beg < e_end) {
-    m_cur = meta(e_beg);
-    m_nxt = meta(clampe(e_beg + 1));
-    const Split s_cur = split(m_cur);
-    m_n2 = meta(clampe(e_beg + 2));
-    s_nxt = split(m_nxt);
-    r_cur = run(m_cur, s_cur);
-  }
-  for (int64_t e = e_beg; e < e_end; ++e) {
-    const Meta m_n3 = meta(clampe(e + 3));
-    s_n2 = split(m_n2);
-    const Run r_nxt = run(m_nxt, s_nxt);
-    if (r_cur.lo + lane < r_cur.hi) accum(r_cur.J, r_cur.p, r_cur.pI, m_cur.lc, m_cur.mc);
-    // runs longer than one wave (supports beyond ~128 nodes) continue in a plain loop
-    for (int b = r_cur.lo + 64 + lane; b < r_cur.hi; b += 64) {
-      const int64_t eb = m_cur.b0 + b;
-      const T pJ[3] = {dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]};
-      accum(gp_nbr[eb], pJ, r_cur.pI, m_cur.lc, m_cur.mc);
+  if constexpr (GW == 1) {
+    // One wave owns the whole upper row.  Point metadata comes 64 points at
+    // a time, one point per lane (the key -> point -> cell -> modulus loads
+    // run once per 64 points), the next 64 loaded while these are used; each
+    // point's fields are then taken by readlane.  The support entries of a
+    // point are loaded kAhead points before its turn (a ring of kAhead runs).
+    constexpr int kAhead = 8;  // divides 64
+    struct LaneMeta {          // lane l: point e0 + l of the batch starting at e0
+      int64_t b0;
+      int n, aI;
+      double lc, mc;
+    };
+    const int64_t cnt = e_end - e_beg;
+    auto load_batch = [&](int64_t i0) {  // points i0 .. i0 + 63 of the row (past the end: the last)
+      LaneMeta v;
+      const int64_t i = i0 + lane < cnt ? i0 + lane : cnt - 1;
+      const uint64_t key = inv_key[e_beg + i];
+      const int64_t g = (int64_t)(key >> 8);
+      v.aI = (int)(key & 255);
+      v.b0 = gp_ptr[g];
+      v.n = (int)(gp_ptr[g + 1] - v.b0);
+      const double c = wdet[g] * E[gp_cell[g]];
+      v.lc = c * lam;
+      v.mc = c * mu;
+      return v;
+    };
+    auto pick = [&](const LaneMeta& v, int j) {  // the batch's point j (j uniform)
+      Meta m;
+      m.b0 = readlane_i64(v.b0, j);
+      m.n = __builtin_amdgcn_readlane(v.n, j);
+      m.aI = __builtin_amdgcn_readlane(v.aI, j);
+      m.lc = readlane_f64(v.lc, j);
+      m.mc = readlane_f64(v.mc, j);
+      return m;
+    };
+    auto run1 = [&](const Meta& m) {  // the upper part of the support: from I's own entry on
+      Run r;
+      r.lo = m.aI;
+      r.hi = m.n;
+      const int b = r.lo + lane;
+      const int bc = b < m.n ? b : m.n - 1;
+      r.J = gp_nbr[m.b0 + bc];
+      for (int k = 0; k < 3; ++k) r.p[k] = dphi[3 * (m.b0 + bc) + k];
+      for (int k = 0; k < 3; ++k) r.pI[k] = dphi[3 * (m.b0 + m.aI) + k];
+      return r;
+    };
+    if (cnt > 0) {
+      LaneMeta cur = load_batch(0), nxt = cur;
+      if (cnt > 64) nxt = load_batch(64);
+      Run ring[kAhead];
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) ring[u] = run1(pick(cur, u < cnt ? u : (int)cnt - 1));
+      for (int64_t i0 = 0; i0 < cnt; i0 += kAhead) {
+        if (i0 > 0 && (i0 & 63) == 0) {  // next batch (uniform)
+          cur = nxt;
+          if (i0 + 64 < cnt) nxt = load_batch(i0 + 64);
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+          const int64_t i = i0 + u;
+          if (i < cnt) {  // uniform
+            const Meta m = pick(cur, (int)(i & 63));
+            const Run& r = ring[u];
+            if (r.lo + lane < r.hi) accum(r.J, r.p, r.pI, m.lc, m.mc);
+            // runs longer than one wave (supports beyond ~128 nodes) continue in a plain loop
+            for (int b = r.lo + 64 + lane; b < r.hi; b += 64) {
+              const int64_t eb = m.b0 + b;
+              const T pJ[3] = {dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]};
+              accum(gp_nbr[eb], pJ, r.pI, m.lc, m.mc);
+            }
+            // refill with point i + kAhead (past the end: the last point again)
+            const int64_t ip = i + kAhead < cnt ? i + kAhead : cnt - 1;
+            const Meta mp = (ip >> 6) == (i0 >> 6) ? pick(cur, (int)(ip & 63)) : pick(nxt, (int)(ip & 63));
+            ring[u] = run1(mp);
+          }
+        }
+      }
     }
-    m_cur = m_nxt;
-    m_nxt = m_n2;
-    m_n2 = m_n3;
-    s_nxt = s_n2;
-    r_cur = r_nxt;
+  } else {
+    const int64_t e_last = e_end - 1;
+    auto clampe = [&](int64_t e) { return e < e_last ? e : e_last; };
+    Meta m_cur = {}, m_nxt = {}, m_n2 = {};
+    Split s_nxt = {}, s_n2 = {};
+    Run r_cur = {};
+    if (e_beg < e_end) {
+      m_cur = meta(e_beg);
+      m_nxt = meta(clampe(e_beg + 1));
+      const Split s_cur = split(m_cur);
+      m_n2 = meta(clampe(e_beg + 2));
+      s_nxt = split(m_nxt);
+      r_cur = run(m_cur, s_cur);
+    }
+    for (int64_t e = e_beg; e < e_end; ++e) {
+      const Meta m_n3 = meta(clampe(e + 3));
+      s_n2 = split(m_n2);
+      const Run r_nxt = run(m_nxt, s_nxt);
+      if (r_cur.lo + lane < r_cur.hi) accum(r_cur.J, r_cur.p, r_cur.pI, m_cur.lc, m_cur.mc);
+      // runs longer than one wave (supports beyond ~128 nodes) continue in a plain loop
+      for (int b = r_cur.lo + 64 + lane; b < r_cur.hi; b += 64) {
+        const int64_t eb = m_cur.b0 + b;
+        const T pJ[3] = {dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]};
+        accum(gp_nbr[eb], pJ, r_cur.pI, m_cur.lc, m_cur.mc);
+      }
+      m_cur = m_nxt;
+      m_nxt = m_n2;
+      m_n2 = m_n3;
+      s_nxt = s_n2;
+      r_cur = r_nxt;
+    }
   }
   __syncthreads();
   // row I: its upper blocks, three contiguous runs of 3 Lu entries (one per row alpha)

@@ -44,6 +44,19 @@ __device__ __forceinline__ int64_t block_pos(const int64_t* blk_ptr, const int32
   return blk_ptr[I] + (int64_t)w.y + __popc(w.x & ((1u << (r & 31)) - 1u));
 }
 
+// 64-bit readlanes: lane L's value of x (L wave-uniform).
+__device__ __forceinline__ double readlane_f64(double x, int L) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, L);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ int64_t readlane_i64(int64_t x, int L) {
+  const int lo = __builtin_amdgcn_readlane((int)x, L);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), L);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 struct Bucket {
   int nmax;        // largest N = n + 4 in the bucket
   int64_t begin;   // range in gp_order

@@ -151,14 +151,6 @@ __device__ __forceinline__ void shift_update(double (&a)[WC], double nl, const d
   }
 }
 
-// 64-bit readlane: lane L's value of x (L wave-uniform).
-__device__ __forceinline__ double readlane_f64(double x, int L) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)b, L);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
 
 // Per-support-node data of the build phase, kept in LDS (the solvers place
 // them inside their U storage, which is written only after the build).
