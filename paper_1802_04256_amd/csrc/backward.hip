@@ -89,59 +89,68 @@ __global__ void __launch_bounds__(kT) k_bwd_rows(const int64_t* blk_ptr, const i
   __syncthreads();
   // Each wave takes four slots at a time, sixteen lanes per slot (lanes over
   // the support of the slot's point), so four independent chains of dependent
-  // loads are in flight per wave.
+  // loads are in flight per wave.  Wave wv's groups start at slots
+  // s_beg + 4 wv + 16 t; the metadata of sixteen groups (64 slots, one per
+  // lane) is loaded at once and handed to each group's lanes by shuffle.
   const int q = lane >> 4, ql = lane & 15;
-  const int64_t e_end = inv_ptr[I + 1];
-  for (int64_t eb = inv_ptr[I] + 4 * wv; eb < e_end; eb += kT / 16) {
-    const int64_t e = eb + q;
-    const bool live = e < e_end;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t b0 = 0;
-    int aI = 0;
-    if (live) {
-      const uint64_t key = inv_key[e];
-      const int64_t g = (int64_t)(key >> 8);
-      aI = (int)(key & 255);
-      b0 = gp_ptr[g];
-      const int n = (int)(gp_ptr[g + 1] - b0);
-      const double w = wdet[g];
-      const double c = w * E[gp_cell[g]];
-      const double lc = c * lam, mc = c * mu, hw = 0.5 * w;
-      const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
+  const int64_t s_beg = inv_ptr[I], e_end = inv_ptr[I + 1];
+  for (int64_t gbase = s_beg + 4 * wv; gbase < e_end; gbase += 16 * (kT / 16)) {
+    // lane l: slot gbase + 16 (l / 4) + l % 4 (past the end: the last slot)
+    const int64_t sl = gbase + 16 * (lane >> 2) + (lane & 3);
+    const uint64_t keyl = inv_key[sl < e_end ? sl : e_end - 1];
+    const int64_t gl = (int64_t)(keyl >> 8);
+    const int64_t b0l = gp_ptr[gl];
+    const int nl = (int)(gp_ptr[gl + 1] - b0l);
+    const double wl = wdet[gl];
+    const double cl = wl * E[gp_cell[gl]];
+    for (int t = 0; t < 16 && gbase + 16 * t < e_end; ++t) {  // uniform
+      const int64_t e = gbase + 16 * t + q;
+      const bool live = e < e_end;
+      const int src = 4 * t + q;
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      const int64_t b0 = __shfl(b0l, src, 64);
+      const int aI = (int)(__shfl((long long)keyl, src, 64) & 255);
+      const int n = __shfl(nl, src, 64);
+      const double w = __shfl(wl, src, 64);
+      const double c = __shfl(cl, src, 64);
+      if (live) {
+        const double lc = c * lam, mc = c * mu, hw = 0.5 * w;
+        const double pI[3] = {dphi[3 * (b0 + aI)], dphi[3 * (b0 + aI) + 1], dphi[3 * (b0 + aI) + 2]};
 #pragma unroll 2
-      for (int b = ql; b < n; b += 16) {
-        const int32_t J = gp_nbr[b0 + b];
-        const int r = J - lo_I;
-        const uint2 bw = bm[r >> 5];
-        const int pos = (int)bw.y + __popc(bw.x & ((1u << (r & 31)) - 1u));
-        const double* Mb = Mrow + 9 * pos;
-        const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
-        const double tr = Mb[0] + Mb[4] + Mb[8];
-        // <M_IJ, k_IJ> with k_IJ = lam pI pb^T + mu pb pI^T + mu (pI . pb) 1 is
-        // lam pI.(M pb) + mu pI.(M^T pb) + mu tr(M) (pI . pb): the products s1 = M pb
-        // and s2 = M^T pb serve both sums
-        // (fused multiply-adds throughout: these sums carry no rounding contract)
-        const double mtr = mc * tr;
-        double d1 = 0.0, d2 = 0.0;
-        for (int ga = 0; ga < 3; ++ga) {
-          const double s1 = __builtin_fma(Mb[3 * ga + 2], pb[2], __builtin_fma(Mb[3 * ga + 1], pb[1], Mb[3 * ga] * pb[0]));
-          const double s2 = __builtin_fma(Mb[6 + ga], pb[2], __builtin_fma(Mb[3 + ga], pb[1], Mb[ga] * pb[0]));
-          v[ga] = __builtin_fma(lc, s1, __builtin_fma(mc, s2, __builtin_fma(mtr, pb[ga], v[ga])));
-          d1 = __builtin_fma(pI[ga], s1, d1);
-          d2 = __builtin_fma(pI[ga], s2, d2);
+        for (int b = ql; b < n; b += 16) {
+          const int32_t J = gp_nbr[b0 + b];
+          const int r = J - lo_I;
+          const uint2 bw = bm[r >> 5];
+          const int pos = (int)bw.y + __popc(bw.x & ((1u << (r & 31)) - 1u));
+          const double* Mb = Mrow + 9 * pos;
+          const double pb[3] = {dphi[3 * (b0 + b)], dphi[3 * (b0 + b) + 1], dphi[3 * (b0 + b) + 2]};
+          const double tr = Mb[0] + Mb[4] + Mb[8];
+          // <M_IJ, k_IJ> with k_IJ = lam pI pb^T + mu pb pI^T + mu (pI . pb) 1 is
+          // lam pI.(M pb) + mu pI.(M^T pb) + mu tr(M) (pI . pb): the products s1 = M pb
+          // and s2 = M^T pb serve both sums
+          // (fused multiply-adds throughout: these sums carry no rounding contract)
+          const double mtr = mc * tr;
+          double d1 = 0.0, d2 = 0.0;
+          for (int ga = 0; ga < 3; ++ga) {
+            const double s1 = __builtin_fma(Mb[3 * ga + 2], pb[2], __builtin_fma(Mb[3 * ga + 1], pb[1], Mb[3 * ga] * pb[0]));
+            const double s2 = __builtin_fma(Mb[6 + ga], pb[2], __builtin_fma(Mb[3 + ga], pb[1], Mb[ga] * pb[0]));
+            v[ga] = __builtin_fma(lc, s1, __builtin_fma(mc, s2, __builtin_fma(mtr, pb[ga], v[ga])));
+            d1 = __builtin_fma(pI[ga], s1, d1);
+            d2 = __builtin_fma(pI[ga], s2, d2);
+          }
+          const double dot = __builtin_fma(pI[2], pb[2], __builtin_fma(pI[1], pb[1], pI[0] * pb[0]));
+          v[3] = __builtin_fma(hw, __builtin_fma(lam, d1, __builtin_fma(mu, d2, (mu * tr) * dot)), v[3]);
         }
-        const double dot = __builtin_fma(pI[2], pb[2], __builtin_fma(pI[1], pb[1], pI[0] * pb[0]));
-        v[3] = __builtin_fma(hw, __builtin_fma(lam, d1, __builtin_fma(mu, d2, (mu * tr) * dot)), v[3]);
       }
-    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = row16_sum(v[i]);
-    if (live && ql == 15) {
-      const int64_t slot = b0 + aI;
-      pbar[3 * slot] = v[0];
-      pbar[3 * slot + 1] = v[1];
-      pbar[3 * slot + 2] = v[2];
-      dEs[slot] = v[3];
+      for (int i = 0; i < 4; ++i) v[i] = row16_sum(v[i]);
+      if (live && ql == 15) {
+        const int64_t slot = b0 + aI;
+        pbar[3 * slot] = v[0];
+        pbar[3 * slot + 1] = v[1];
+        pbar[3 * slot + 2] = v[2];
+        dEs[slot] = v[3];
+      }
     }
   }
 }
