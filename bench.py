@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/shape_panel.hip",
                  "paper_1802_04256_amd/csrc/shape_common.h", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "1d5eefe6590b9252d23a4ebea3c4e10ef7f872cdb3a8d6e80def3fca5f9b077b", "bytes_per_step": 3.4490e10}
+SHAPE_TRAFFIC = {"sources_sha256": "0028fe30ba27c935994e48bbdf1ee48819bd40e390ea0642b6dfdb495de76dd1", "bytes_per_step": 3.4509e10}
 
 
 def log(*a):
