@@ -262,37 +262,76 @@ __global__ void __launch_bounds__(256) k_blocks_union(const int64_t* inv_ptr, co
   for (int i = threadIdx.x; i < nw; i += blockDim.x) bm[i] = 0u;
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // each wave takes every fourth point of I's list; the next point's support
-  // range is loaded while this point's ids are read and entered
-  const int64_t e1 = inv_ptr[I + 1];
-  int64_t e = inv_ptr[I] + w;
-  int64_t bn = 0, nn = 0;
-  if (e < e1) {
-    const int64_t g = (int64_t)(inv_key[e] >> 8);
-    bn = gp_ptr[g];
-    nn = gp_ptr[g + 1] - bn;
-  }
-  for (; e < e1; e += 4) {
-    const int64_t b = bn, n = nn;
-    int32_t id0 = 0, id1 = 0;
-    if (lane < n) id0 = gp_nbr[b + lane];
-    if (lane + 64 < n) id1 = gp_nbr[b + lane + 64];
-    if (e + 4 < e1) {
-      const int64_t g = (int64_t)(inv_key[e + 4] >> 8);
-      bn = gp_ptr[g];
-      nn = gp_ptr[g + 1] - bn;
+  // Each wave takes every fourth point of I's list.  The support ranges of
+  // 64 of its points are loaded at once, one point per lane (the key ->
+  // point -> range loads run once per 64 points), and taken by readlane;
+  // each point's ids are loaded kAhead points before they are entered.
+  constexpr int kAhead = 8;  // divides 64
+  const int64_t e0 = inv_ptr[I] + w, e1 = inv_ptr[I + 1];
+  const int64_t cnt_w = e0 < e1 ? (e1 - e0 + 3) / 4 : 0;  // this wave's points: e0 + 4 k
+  struct Ids {
+    int32_t id0, id1;  // support entries lane and lane + 64 (clamped to the last)
+  };
+  auto load_batch = [&](int64_t k0, int64_t& b, int& n) {  // lane l: point k0 + l (past the end: the last)
+    const int64_t k = k0 + lane < cnt_w ? k0 + lane : cnt_w - 1;
+    const int64_t g = (int64_t)(inv_key[e0 + 4 * k] >> 8);
+    b = gp_ptr[g];
+    n = (int)(gp_ptr[g + 1] - b);
+  };
+  auto ids = [&](int64_t b, int n) {
+    Ids r;
+    r.id0 = gp_nbr[b + (lane < n ? lane : n - 1)];
+    r.id1 = gp_nbr[b + (lane + 64 < n ? lane + 64 : n - 1)];
+    return r;
+  };
+  if (cnt_w > 0) {
+    int64_t bc = 0, bx = 0;
+    int nc = 0, nx = 0;
+    load_batch(0, bc, nc);
+    bx = bc;
+    nx = nc;
+    if (cnt_w > 64) load_batch(64, bx, nx);
+    Ids ring[kAhead];
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u) {
+      const int j = u < cnt_w ? u : (int)cnt_w - 1;
+      ring[u] = ids(readlane_i64(bc, j), __builtin_amdgcn_readlane(nc, j));
     }
-    if (lane < n) {
-      const int r = id0 - lo;
-      atomicOr(&bm[r >> 5], 1u << (r & 31));
-    }
-    if (lane + 64 < n) {
-      const int r = id1 - lo;
-      atomicOr(&bm[r >> 5], 1u << (r & 31));
-    }
-    for (int64_t a = lane + 128; a < n; a += 64) {  // supports above 128 nodes
-      const int r = gp_nbr[b + a] - lo;
-      atomicOr(&bm[r >> 5], 1u << (r & 31));
+    for (int64_t k0 = 0; k0 < cnt_w; k0 += kAhead) {
+      if (k0 > 0 && (k0 & 63) == 0) {  // next batch (uniform)
+        bc = bx;
+        nc = nx;
+        if (k0 + 64 < cnt_w) load_batch(k0 + 64, bx, nx);
+      }
+#pragma unroll
+      for (int u = 0; u < kAhead; ++u) {
+        const int64_t k = k0 + u;
+        if (k < cnt_w) {  // uniform
+          const int j = (int)(k & 63);
+          const int64_t b = readlane_i64(bc, j);
+          const int n = __builtin_amdgcn_readlane(nc, j);
+          const Ids r = ring[u];
+          if (lane < n) {
+            const int rr = r.id0 - lo;
+            atomicOr(&bm[rr >> 5], 1u << (rr & 31));
+          }
+          if (lane + 64 < n) {
+            const int rr = r.id1 - lo;
+            atomicOr(&bm[rr >> 5], 1u << (rr & 31));
+          }
+          for (int64_t a = lane + 128; a < n; a += 64) {  // supports above 128 nodes
+            const int rr = gp_nbr[b + a] - lo;
+            atomicOr(&bm[rr >> 5], 1u << (rr & 31));
+          }
+          // refill with point k + kAhead (past the end: the last point again)
+          const int64_t kp = k + kAhead < cnt_w ? k + kAhead : cnt_w - 1;
+          const int jp = (int)(kp & 63);
+          if ((kp >> 6) == (k0 >> 6))
+            ring[u] = ids(readlane_i64(bc, jp), __builtin_amdgcn_readlane(nc, jp));
+          else
+            ring[u] = ids(readlane_i64(bx, jp), __builtin_amdgcn_readlane(nx, jp));
+        }
+      }
     }
   }
   __syncthreads();
