@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(64 * GW) k_rowgather(const int64_t* blk_ptr, c
             const Meta m = pick(cur, (int)(i & 63));
             const Run& r = ring[u];
             if (r.lo + lane < r.hi) accum(r.J, r.p, r.pI, m.lc, m.mc);
-            // runs longer than one wave (supports beyond ~128 nodes) continue in a plain loop
+            // upper parts longer than one wave (over 64 entries) continue in a plain loop
             for (int b = r.lo + 64 + lane; b < r.hi; b += 64) {
               const int64_t eb = m.b0 + b;
               const T pJ[3] = {dphi[3 * eb], dphi[3 * eb + 1], dphi[3 * eb + 2]};
