@@ -94,3 +94,29 @@ def test_backward_refuses_factors_of_another_forward():
     assert ei.value.code == -8
     with pytest.raises(rp.RpimError):
         rp._check_factors(Plan(3), 0)  # the forward kept nothing
+
+
+def test_tuning_cache_file_round_trip_and_validation(tmp_path):
+    # host-only: the text cache keeps solver and gather choices; gather
+    # configurations are 1 to 4 waves per row, solver kinds 0 to 3
+    import paper_1802_04256_amd as rp
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\ngfx950 fp64 gather 0 1\ngfx950 mixed gather 0 4\ngfx950 fp64 solver 80 2\n")
+    rp.tuning_cache(clear=True)
+    try:
+        rp.tuning_cache(load=str(good))
+        out = tmp_path / "out.txt"
+        rp.tuning_cache(save=str(out))
+        lines = sorted(l for l in out.read_text().splitlines() if not l.startswith("#"))
+        assert lines == ["gfx950 fp64 gather 0 1", "gfx950 fp64 solver 80 2", "gfx950 mixed gather 0 4"]
+        for bad in ("gfx950 fp64 gather 0 0", "gfx950 fp64 gather 0 5", "gfx950 fp32 gather 0 1",
+                    "gfx950 fp64 solver 80 9", "gfx950 fp64 other 0 1", "gfx950 fp64 gather"):
+            f = tmp_path / "bad.txt"
+            f.write_text(bad + "\n")
+            with pytest.raises(rp.RpimError) as ei:
+                rp.tuning_cache(load=str(f))
+            assert ei.value.code == -1, bad
+        with pytest.raises(rp.RpimError):
+            rp.tuning_cache(load=str(tmp_path / "missing.txt"))
+    finally:
+        rp.tuning_cache(clear=True)
