@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 SHAPE_SOURCES = ("paper_1802_04256_amd/csrc/shape_reg.hip", "paper_1802_04256_amd/csrc/shape_panel.hip",
                  "paper_1802_04256_amd/csrc/shape_common.h", "paper_1802_04256_amd/csrc/assemble.hip",
                  "paper_1802_04256_amd/csrc/dd_pow.h", "paper_1802_04256_amd/csrc/rpim_internal.h")
-SHAPE_TRAFFIC = {"sources_sha256": "90b710f08be523e5b1f00673ce29976ca79023937c17c25562ef6d457a5018f4", "bytes_per_step": 3.4509e10}
+SHAPE_TRAFFIC = {"sources_sha256": "90b710f08be523e5b1f00673ce29976ca79023937c17c25562ef6d457a5018f4", "bytes_per_step": 3.4496e10}
 
 
 def log(*a):
